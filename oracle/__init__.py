@@ -1,0 +1,27 @@
+"""CPU float64 oracle of the back-and-forth method -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import, call, link or execute anything in this package.  It
+shares no code with the HIP path (``paper_1905_12154_amd``) and neither imports
+the other; both consume the seeded densities of
+``paper_1905_12154_amd.workloads``, which hold none of the method's arithmetic.
+
+Pins (see tests/test_oracle_*.py):
+  * ctransform       -- non-separable brute force of the definition, c-transform
+                        identities (Lemma on c-transform properties, (i)),
+                        closed form for linear potentials.
+  * poisson_neumann  -- residual of the second-difference stencil applied
+                        directly, sparse direct solve, summation-by-parts for G.
+  * pushforward      -- mass conservation, identity map, whole-cell shifts,
+                        adjointness with multilinear interpolation (scipy).
+  * update_sigma     -- scripted sequences against the Section 4.2 rule.
+  * solve            -- exact costs of the Section 4.3 examples (discs 1/4,
+                        squares 1/16, translations |a|^2/2), weak duality
+                        against the exact discrete LP (HiGHS) on tiny grids,
+                        the unconditional c-transform half of the monotone
+                        chain, Gaussian-to-Gaussian affine maps.
+  * w2_gradients     -- parity unpinned beyond finite differences of the
+                        oracle's own value (the discretised pushforward adds an
+                        envelope error of the order of the discretisation).
+"""
+from . import bfm  # noqa: F401
