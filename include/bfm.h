@@ -1,0 +1,177 @@
+/*
+ * bfm.h -- C ABI of the MI355X (gfx950) back-and-forth optimal-transport library.
+ *
+ * Problem (paper: Jacobs & Leger, "A fast approach to optimal transport: the
+ * back-and-forth method", Section 3, eq. dual): given two probability
+ * densities mu, nu on the uniform grid of Omega = [0,1]^d (d = 2 or 3,
+ * Section 4.3) and the quadratic cost c(x,y) = |x-y|^2 / 2, maximise the
+ * Kantorovich dual J(phi) = int phi dnu + int phi^c dmu (eq. defJ) by the
+ * back-and-forth iteration (Algorithm 1) with H^1 gradient steps
+ * (eq. gradients_J_I) and the adaptive step size of Section 4.2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid:    shape[0..ndim-1] cells per axis, row-major, axis ndim-1 contiguous.
+ *          Cells are centred: x = (i + 1/2) / n_a on axis a.  N = prod(shape).
+ * Fields:  device arrays of N elements of the plan's dtype (float or double),
+ *          owned and allocated by the caller.  A density f is given by its
+ *          grid values with cell_volume * sum(f) = 1.
+ * Maps:    T is ndim planar fields (T_0 then T_1 ...), each N elements, in
+ *          physical coordinates, clamped to [h_a/2, 1 - h_a/2].
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *          Work is enqueued asynchronously on it.  Entry points that return
+ *          host scalars synchronise that stream before returning.
+ * Memory:  the library never allocates device memory.  Every call that needs
+ *          scratch takes a caller-owned device `workspace` of at least
+ *          bfm_plan_workspace_bytes() bytes, 256-byte aligned, not shared
+ *          between calls that may run concurrently.  A plan owns host memory
+ *          only.
+ * Errors:  every call returns a bfm_status; no exception crosses the ABI.
+ *          Argument validation happens before any launch.  The message of the
+ *          last failure on the calling thread is returned by bfm_last_error().
+ */
+#ifndef BFM_H
+#define BFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BFM_OK = 0,
+    BFM_EINVAL = 1,        /* invalid argument: null pointer, bad shape, bad density ... */
+    BFM_EDEVICE = 2,       /* a HIP call failed (launch, copy, synchronise) */
+    BFM_ENUMERIC = 3,      /* a non-finite value appeared in the device state */
+    BFM_EWORKSPACE = 4,    /* workspace pointer null, misaligned or too small */
+    BFM_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+} bfm_status;
+
+typedef enum { BFM_F32 = 0, BFM_F64 = 1 } bfm_dtype;
+
+/* Solver parameters.  Defaults (bfm_params_init) are the paper's Section 4.2
+ * constants: sigma_min = 0.01, beta1 = 1/4, beta2 = 3/4, alpha1 = 5/4,
+ * alpha2 = 4/5, and sigma0 <= 0 meaning 8 min(1/max mu, 1/max nu). */
+typedef struct {
+    int32_t ndim;          /* 2 or 3 */
+    int32_t shape[3];      /* cells per axis, each 4 <= n <= 4096 and of the form 2^a 3^b */
+    int32_t dtype;         /* bfm_dtype: storage and arithmetic type of fields; sums are float64 */
+    int32_t max_iters;     /* full back-and-forth iterations (phi-step + psi-step) */
+    double tol;            /* stop when gap < tol; 0 runs max_iters iterations */
+    double sigma0;         /* initial step; <= 0 selects 8 min(1/max mu, 1/max nu) */
+    double sigma_min;
+    double beta1, beta2, alpha1, alpha2;
+    int32_t check_every;   /* iterations enqueued between host reads of the stop flag (>= 1) */
+    int32_t reserved;
+} bfm_params;
+
+/* Per-solve report (host struct). gap = max(|primal - dual|, G) at the last
+ * evaluated head, G = ||nu - T#mu||^2 in H^-1 (squared H^1 norm of the gradient). */
+typedef struct {
+    int32_t iters;         /* completed full iterations */
+    int32_t converged;     /* 1 when gap < tol stopped the loop */
+    int32_t status;        /* bfm_status of the solve */
+    int32_t reserved;
+    double dual;           /* J(phi) = C(mu,nu) estimate = W2^2 / 2 */
+    double primal;         /* int |x - T(x)|^2 / 2 dmu */
+    double gap;
+    double G;
+    double sigma;          /* step size after the last update */
+    double mass_mu, mass_nu;  /* cell_volume * sum, as read on the device */
+} bfm_result;
+
+typedef struct bfm_plan_s *bfm_plan;
+
+/* Fill `p` with the defaults for a grid; returns BFM_EINVAL on a bad shape. */
+bfm_status bfm_params_init(bfm_params *p, int32_t ndim, const int32_t *shape, int32_t dtype);
+
+/* Validate parameters and build the host-side plan (spectral tables, launch
+ * shapes).  Host only: no device call.  *out receives a plan to be released
+ * with bfm_plan_destroy. */
+bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out);
+void bfm_plan_destroy(bfm_plan plan);
+
+/* Bytes of device workspace every call on this plan needs. */
+bfm_status bfm_plan_workspace_bytes(bfm_plan plan, size_t *bytes);
+
+/* Back-and-forth solve (Algorithm 1, step rule of Section 4.2).
+ *   mu, nu     device, N elements each: source and target densities (read only).
+ *              Rejected with BFM_EINVAL (before any iteration) if a value is
+ *              negative or non-finite or |cell_volume*sum - 1| > 1e-5.
+ *   phi_init   device, N elements or NULL (NULL: phi_0 = 0).  Warm start/resume.
+ *   phi, psi   device outputs, N elements each: phi - mean(phi) and
+ *              psi = phi^c + mean(phi), an exactly c-conjugate pair.
+ *              Also used as working buffers during the solve.
+ *   T          device output, ndim*N elements, or NULL: the map x - grad psi.
+ *   result     host output (may be NULL).
+ * Synchronises `stream` every check_every iterations to read the stop flag.
+ * Not reaching tol within max_iters is not an error (converged = 0). */
+bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *phi_init,
+                     void *phi, void *psi, void *T, void *workspace, size_t ws_bytes,
+                     void *stream, bfm_result *result);
+
+/* Primitive: quadratic-cost c-transform on the grid (Definition of the
+ * c-transform; separable evaluation of Section 4.1; per line the Legendre
+ * transform on the lower convex hull, eq. legendre / legendre_search):
+ *   out(x) = min over grid points y of |x - y|^2 / 2 - in(y).
+ * in and out are device fields of N elements; out may equal in. */
+bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/* Primitive: map and pushforward (Lemma on c-transform properties (ii) with
+ * h = |.|^2/2; pushforward of Section 2.1).  T = x - grad phic (central
+ * differences, one-sided at faces, clamped to the cell-centre box) and
+ * rho = T#mass by cloud-in-cell deposition (multilinear weights).
+ *   phic, mass  device inputs, N elements.
+ *   rho         device output density, N elements (overwritten).
+ *   T           device output, ndim*N elements, or NULL.
+ *   primal      host output or NULL: int |x - T(x)|^2/2 dmass (synchronises). */
+bfm_status bfm_pushforward(bfm_plan plan, const void *phic, const void *mass, void *rho, void *T,
+                           double *primal, void *workspace, size_t ws_bytes, void *stream);
+
+/* Primitive: H^1 gradient (H^1-gradient lemma, eq. gradients_J_I):
+ * g = (-Laplacian)^{-1}(f - mean f) with zero-flux Neumann data, the
+ * Laplacian being the second-difference stencil diagonalised by the DCT-II
+ * (inversion by FFT, Section 4.3).
+ *   f  device input, N elements (read only); g device output, N elements.
+ *   G  host output or NULL: cell_volume * sum(f g) = ||f - mean f||^2_{H^-1}
+ *      (synchronises). */
+bfm_status bfm_poisson_neumann(bfm_plan plan, const void *f, void *g, double *G,
+                               void *workspace, size_t ws_bytes, void *stream);
+
+/* Gradient of W2^2 = 2 C(mu,nu) with respect to the grid density values at a
+ * converged pair (first variation of J, Lemma fact:derivative-J, envelope
+ * form): grad_mu = scale * 2 cell_volume (psi - mean psi),
+ * grad_nu = scale * 2 cell_volume (phi - mean phi).  Either output may be NULL. */
+bfm_status bfm_grad(bfm_plan plan, const void *phi, const void *psi, double scale,
+                    void *grad_mu, void *grad_nu, void *workspace, size_t ws_bytes, void *stream);
+
+/* Primitive: one separable pass of the c-transform along `axis` (the
+ * one-dimensional step of Section 4.1): for every grid line along that axis
+ *   out_i = min_j (x_i - y_j)^2 / 2 + sign * in_j .
+ * sign is +1 or -1 (the first pass of a transform uses -1).  in/out are
+ * device fields of N elements; out may equal in.  Exposed for measurement
+ * and tests. */
+bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t sign, const void *in, void *out,
+                               void *stream);
+
+/* Copy the per-iteration trace of the last bfm_solve run on `workspace`
+ * to host memory: record r is 8 doubles (iteration, dual J(phi_n), primal
+ * P_n, G_n, gap_n, sigma_n, J(phi_{n+1/2}), I(psi_{n+1})) taken at the head of
+ * iteration n.  Up to max_records records are copied; *count receives the
+ * number recorded (which may exceed max_records).  Synchronises `stream`. */
+bfm_status bfm_trace(bfm_plan plan, const void *workspace, size_t ws_bytes, double *host, int32_t max_records,
+                     int32_t *count, void *stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char *bfm_last_error(void);
+
+/* Library version string. */
+const char *bfm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFM_H */

@@ -1,0 +1,313 @@
+"""Python binding of ``libbfm.so`` (the C ABI declared in ``include/bfm.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are PyTorch CUDA (ROCm) tensors, contiguous, of the plan's
+dtype (float32 or float64); work is enqueued on the current PyTorch stream.
+If the library is not built this module raises instead of computing anything
+another way.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbfm.so")
+
+BFM_OK, BFM_EINVAL, BFM_EDEVICE, BFM_ENUMERIC, BFM_EWORKSPACE, BFM_EUNSUPPORTED = range(6)
+BFM_F32, BFM_F64 = 0, 1
+STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC", 4: "BFM_EWORKSPACE",
+                5: "BFM_EUNSUPPORTED"}
+EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
+            "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
+            "bfm_version", "bfm_ctransform_axis", "bfm_trace"]
+
+
+class BFMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("shape", ctypes.c_int32 * 3), ("dtype", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("sigma0", ctypes.c_double),
+                ("sigma_min", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("alpha1", ctypes.c_double), ("alpha2", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("dual", ctypes.c_double), ("primal", ctypes.c_double),
+                ("gap", ctypes.c_double), ("G", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("mass_mu", ctypes.c_double), ("mass_nu", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libbfm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libbfm.so is not built (%s); run `python -m paper_1905_12154_amd.build_lib`"
+                               % _LIB_PATH)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, sz, i32, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+        P = ctypes.POINTER
+        L.bfm_params_init.argtypes = [P(Params), i32, P(i32), i32]
+        L.bfm_plan_create.argtypes = [P(Params), P(vp)]
+        L.bfm_plan_destroy.argtypes = [vp]
+        L.bfm_plan_destroy.restype = None
+        L.bfm_plan_workspace_bytes.argtypes = [vp, P(sz)]
+        L.bfm_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, P(Result)]
+        L.bfm_ctransform.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.bfm_pushforward.argtypes = [vp, vp, vp, vp, vp, P(dbl), vp, sz, vp]
+        L.bfm_poisson_neumann.argtypes = [vp, vp, vp, P(dbl), vp, sz, vp]
+        L.bfm_grad.argtypes = [vp, vp, vp, dbl, vp, vp, vp, sz, vp]
+        L.bfm_ctransform_axis.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
+        L.bfm_last_error.argtypes = []
+        L.bfm_last_error.restype = ctypes.c_char_p
+        L.bfm_version.argtypes = []
+        L.bfm_version.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("bfm_plan_destroy", "bfm_last_error", "bfm_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != BFM_OK:
+        raise BFMError(status, lib().bfm_last_error().decode())
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (torch.float32, "float32", "f32", BFM_F32):
+        return BFM_F32
+    if dtype in (torch.float64, "float64", "f64", BFM_F64):
+        return BFM_F64
+    raise ValueError("dtype must be float32 or float64")
+
+
+def _torch_dtype(code: int):
+    return torch.float64 if code == BFM_F64 else torch.float32
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """Host plan for one grid shape and dtype (``bfm_plan_create``) plus a
+    cached device workspace."""
+
+    def __init__(self, shape: Sequence[int], dtype=torch.float32, max_iters: int = 60, tol: float = 0.0,
+                 sigma0: float = 0.0, sigma_min: float = 0.01, beta1: float = 0.25, beta2: float = 0.75,
+                 alpha1: float = 1.25, alpha2: float = 0.8, check_every: int = 8):
+        L = lib()
+        self.shape = tuple(int(s) for s in shape)
+        self.code = _dtype_code(dtype)
+        self.dtype = _torch_dtype(self.code)
+        p = Params()
+        shp = (ctypes.c_int32 * 3)(*(list(self.shape) + [1] * (3 - len(self.shape))))
+        _check(L.bfm_params_init(ctypes.byref(p), len(self.shape), shp, self.code))
+        p.max_iters, p.tol, p.sigma0, p.sigma_min = int(max_iters), float(tol), float(sigma0), float(sigma_min)
+        p.beta1, p.beta2, p.alpha1, p.alpha2 = float(beta1), float(beta2), float(alpha1), float(alpha2)
+        p.check_every = int(check_every)
+        self.params = p
+        h = ctypes.c_void_p()
+        _check(L.bfm_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(L.bfm_plan_workspace_bytes(h, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.bfm_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, device) -> torch.Tensor:
+        device = torch.device(device)
+        ws = self._ws.get(device)
+        if ws is None:
+            ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+            self._ws[device] = ws
+        off = (-ws.data_ptr()) % 256
+        return ws[off:off + self.ws_bytes]
+
+    def _field(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+        if tuple(t.shape) != self.shape:
+            raise ValueError("%s has shape %s, plan is %s" % (name, tuple(t.shape), self.shape))
+        if t.dtype != self.dtype:
+            raise TypeError("%s has dtype %s, plan is %s" % (name, t.dtype, self.dtype))
+        return t.contiguous()
+
+    # -- entry points --------------------------------------------------
+    def solve(self, mu, nu, phi_init=None, return_map: bool = True):
+        mu = self._field(mu, "mu")
+        nu = self._field(nu, "nu")
+        dev = mu.device
+        pi = None if phi_init is None else self._field(phi_init, "phi_init")
+        phi = torch.empty_like(mu)
+        psi = torch.empty_like(mu)
+        T = torch.empty((len(self.shape),) + self.shape, dtype=self.dtype, device=dev) if return_map else None
+        ws = self.workspace(dev)
+        res = Result()
+        _check(lib().bfm_solve(self._h, _ptr(mu), _ptr(nu), _ptr(pi), _ptr(phi), _ptr(psi), _ptr(T),
+                               _ptr(ws), self.ws_bytes, _stream(dev), ctypes.byref(res)))
+        return SolveResult(phi=phi, psi=psi, T=T, dual=res.dual, primal=res.primal, gap=res.gap, G=res.G,
+                           sigma=res.sigma, iters=res.iters, converged=bool(res.converged),
+                           mass_mu=res.mass_mu, mass_nu=res.mass_nu)
+
+    def ctransform_axis(self, f, axis: int, sign: int = -1, out=None):
+        f = self._field(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        _check(lib().bfm_ctransform_axis(self._h, int(axis), int(sign), _ptr(f), _ptr(out), _stream(f.device)))
+        return out
+
+    def trace(self, device) -> List[dict]:
+        """Per-iteration records of the last solve on this plan's workspace."""
+        ws = self.workspace(device)
+        cnt = ctypes.c_int32()
+        _check(lib().bfm_trace(self._h, _ptr(ws), self.ws_bytes, None, 0, ctypes.byref(cnt), _stream(device)))
+        m = min(int(cnt.value), 4096)
+        buf = (ctypes.c_double * (8 * max(m, 1)))()
+        _check(lib().bfm_trace(self._h, _ptr(ws), self.ws_bytes, buf, m, ctypes.byref(cnt), _stream(device)))
+        keys = ("iter", "dual", "primal", "G", "gap", "sigma", "J_half", "I_new")
+        return [dict(zip(keys, buf[8 * r:8 * r + 8])) for r in range(m)]
+
+    def ctransform(self, f, out=None):
+        f = self._field(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        ws = self.workspace(f.device)
+        _check(lib().bfm_ctransform(self._h, _ptr(f), _ptr(out), _ptr(ws), self.ws_bytes, _stream(f.device)))
+        return out
+
+    def pushforward(self, phic, mass, return_map: bool = True):
+        phic = self._field(phic, "phic")
+        mass = self._field(mass, "mass")
+        rho = torch.empty_like(mass)
+        T = torch.empty((len(self.shape),) + self.shape, dtype=self.dtype, device=mass.device) \
+            if return_map else None
+        P = ctypes.c_double()
+        ws = self.workspace(mass.device)
+        _check(lib().bfm_pushforward(self._h, _ptr(phic), _ptr(mass), _ptr(rho), _ptr(T), ctypes.byref(P),
+                                     _ptr(ws), self.ws_bytes, _stream(mass.device)))
+        return rho, T, P.value
+
+    def poisson_neumann(self, f):
+        f = self._field(f, "f")
+        g = torch.empty_like(f)
+        G = ctypes.c_double()
+        ws = self.workspace(f.device)
+        _check(lib().bfm_poisson_neumann(self._h, _ptr(f), _ptr(g), ctypes.byref(G), _ptr(ws), self.ws_bytes,
+                                         _stream(f.device)))
+        return g, G.value
+
+    def grad(self, phi, psi, scale: float = 1.0):
+        phi = self._field(phi, "phi")
+        psi = self._field(psi, "psi")
+        gmu = torch.empty_like(psi)
+        gnu = torch.empty_like(phi)
+        ws = self.workspace(phi.device)
+        _check(lib().bfm_grad(self._h, _ptr(phi), _ptr(psi), float(scale), _ptr(gmu), _ptr(gnu), _ptr(ws),
+                              self.ws_bytes, _stream(phi.device)))
+        return gmu, gnu
+
+
+@dataclass
+class SolveResult:
+    phi: torch.Tensor
+    psi: torch.Tensor
+    T: Optional[torch.Tensor]
+    dual: float
+    primal: float
+    gap: float
+    G: float
+    sigma: float
+    iters: int
+    converged: bool
+    mass_mu: float
+    mass_nu: float
+
+    @property
+    def w2sq(self) -> float:
+        """W2^2 = 2 C(mu, nu) for c = |x-y|^2/2."""
+        return 2.0 * self.dual
+
+
+_plans = {}
+
+
+def plan_for(shape, dtype, **kw) -> Plan:
+    key = (tuple(shape), _dtype_code(dtype), tuple(sorted(kw.items())))
+    p = _plans.get(key)
+    if p is None:
+        p = Plan(shape, dtype, **kw)
+        _plans[key] = p
+    return p
+
+
+def solve(mu: torch.Tensor, nu: torch.Tensor, phi_init=None, return_map=True, **kw) -> SolveResult:
+    """Back-and-forth solve of quadratic-cost OT between grid densities."""
+    return plan_for(mu.shape, mu.dtype, **kw).solve(mu, nu, phi_init=phi_init, return_map=return_map)
+
+
+def ctransform(f: torch.Tensor) -> torch.Tensor:
+    return plan_for(f.shape, f.dtype).ctransform(f)
+
+
+def pushforward(phic: torch.Tensor, mass: torch.Tensor, return_map=True):
+    return plan_for(phic.shape, phic.dtype).pushforward(phic, mass, return_map=return_map)
+
+
+def poisson_neumann(f: torch.Tensor):
+    return plan_for(f.shape, f.dtype).poisson_neumann(f)
+
+
+class W2Loss(torch.autograd.Function):
+    """W2^2(mu, nu) = 2 C(mu, nu) from a back-and-forth solve; the backward
+    pass returns the converged Kantorovich potentials (mean-zeroed, scaled by
+    2 cell_volume) as the gradients w.r.t. the grid density values."""
+
+    @staticmethod
+    def forward(ctx, mu, nu, max_iters=200, tol=1e-6):
+        plan = plan_for(mu.shape, mu.dtype, max_iters=max_iters, tol=tol)
+        r = plan.solve(mu.detach().contiguous(), nu.detach().contiguous(), return_map=False)
+        ctx.plan = plan
+        ctx.save_for_backward(r.phi, r.psi)
+        return torch.tensor(r.w2sq, dtype=torch.float64, device=mu.device).to(mu.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        phi, psi = ctx.saved_tensors
+        gmu, gnu = ctx.plan.grad(phi, psi, float(grad_out))
+        return gmu, gnu, None, None
+
+
+def w2_loss(mu, nu, max_iters=200, tol=1e-6):
+    return W2Loss.apply(mu, nu, max_iters, tol)

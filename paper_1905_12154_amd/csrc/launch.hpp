@@ -1,0 +1,72 @@
+// Host-side launchers shared between the library's translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace bfm {
+
+// Per-axis spectral plan: FFT radix sequence (2 bits per stage: 0 -> 4,
+// 2 -> 2, 3 -> 3) and the stride of the axis.
+struct AxisPlan {
+    int n;
+    int inner;
+    uint32_t radices;
+    int nstages;
+};
+
+// c-transform (ctransform.hip)
+template <typename T>
+hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream);
+template <typename T>
+hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
+                          const int32_t *done, hipStream_t stream);
+int ct_threads_per_line(int n);
+template <typename T> size_t ct_smem_bytes(int n, int tpl, int lpb);
+
+// DCT Poisson (dct.hip)
+template <typename T>
+hipError_t launch_dct2_axis(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b,
+                            const void *tw, const void *qw, const int32_t *done, hipStream_t stream);
+template <typename T>
+hipError_t launch_dct3_axis(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap,
+                            long long N, const void *tw, const void *qw, const int32_t *done,
+                            hipStream_t stream);
+template <typename T>
+hipError_t launch_spectral_divide(T *X, const Grid &g, const T *lam0, const T *lam1, const T *lam2,
+                                  double *part, int nblocks, const int32_t *done, hipStream_t stream);
+
+// map, pushforward, reductions, controller (pushforward.hip, reduce.hip)
+template <typename T>
+hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
+                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream);
+template <typename T>
+hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long long N, double *part1,
+                       double *part2, int nblocks, const int32_t *done, hipStream_t stream);
+template <typename T>
+hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, int nblocks,
+                        hipStream_t stream);
+template <typename T>
+hipError_t launch_fill(T *x, long long N, T value, hipStream_t stream);
+template <typename T>
+hipError_t launch_shift_scale(T *out_a, const T *in_a, const double *shift_a, double sign_a, T *out_b,
+                              const T *in_b, const double *shift_b, double sign_b, long long N, double mul,
+                              hipStream_t stream);
+
+// Controller modes
+enum CtrlMode {
+    CTRL_INIT = 0,     // masses, extrema, sigma0
+    CTRL_HEAD_PHI,     // J(phi_n), P_n, G_n, gap, stop test, trace
+    CTRL_STEP_PHI,     // J(phi_{n+1/2}) and the sigma update
+    CTRL_HEAD_PSI,     // I(psi_{n+1/2}), G
+    CTRL_STEP_PSI,     // I(psi_{n+1}), sigma update, iteration count
+    CTRL_MEANS         // mean_a, mean_b from S_MEAN_A / S_MEAN_B
+};
+
+struct CtrlParams {
+    double tol, sigma0, sigma_min, beta1, beta2, alpha1, alpha2, vol, inv_N;
+};
+
+hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, int mode, CtrlParams prm,
+                       TraceRec *trace, hipStream_t stream);
+
+}  // namespace bfm

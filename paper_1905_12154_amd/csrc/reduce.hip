@@ -1,0 +1,278 @@
+// Float64 reductions, elementwise helpers and the on-device step-size controller.
+//
+// The dual functionals J(phi) = int phi dnu + int phi^c dmu and
+// I(psi) = int psi dmu + int psi^c dnu (eq. defJ / defI) are cell-volume
+// weighted sums.  Every sum is accumulated in float64 from per-block partials
+// reduced by one controller block in a fixed order, so results do not depend
+// on scheduling.  The controller applies the Section 4.2 rule after each
+// gradient step: with increase = J(p + sigma g) - J(p) and G = ||grad||^2_{H^1},
+// keep sigma when beta1 sigma G <= increase <= beta2 sigma G, otherwise
+// shrink by alpha2 (not below sigma_min) or grow by alpha1; no backtracking.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace bfm {
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock)
+dot2_kernel(const T *__restrict__ a1, const T *__restrict__ b1, const T *__restrict__ a2,
+            const T *__restrict__ b2, long long N, double *__restrict__ part1, double *__restrict__ part2,
+            const int32_t *__restrict__ done)
+{
+    if (done != nullptr && *done) return;
+    __shared__ double sh[kRedBlock / kWave];
+    double s1 = 0.0, s2 = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        s1 += (double)a1[i] * (b1 != nullptr ? (double)b1[i] : 1.0);
+        if (a2 != nullptr) s2 += (double)a2[i] * (double)b2[i];
+    }
+    s1 = block_reduce<R_SUM>(s1, sh);
+    if (threadIdx.x == 0) part1[blockIdx.x] = s1;
+    if (a2 != nullptr) {
+        s2 = block_reduce<R_SUM>(s2, sh);
+        if (threadIdx.x == 0) part2[blockIdx.x] = s2;
+    }
+}
+
+template <typename T>
+hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long long N, double *part1,
+                       double *part2, int nblocks, const int32_t *done, hipStream_t stream)
+{
+    hipLaunchKernelGGL((dot2_kernel<T>), dim3(nblocks), dim3(kRedBlock), 0, stream, a1, b1, a2, b2, N, part1,
+                       part2, done);
+    return hipGetLastError();
+}
+
+// Sums, extrema and a count of invalid (negative or non-finite) values of mu, nu.
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock)
+stats_kernel(const T *__restrict__ mu, const T *__restrict__ nu, long long N, double *__restrict__ partials)
+{
+    __shared__ double sh[kRedBlock / kWave];
+    double smu = 0, snu = 0, xmu = -INFINITY, xnu = -INFINITY, nmu = INFINITY, nnu = INFINITY, bad = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double a = (double)mu[i], b = (double)nu[i];
+        if (!(isfinite(a) && a >= 0.0)) bad += 1.0;
+        if (!(isfinite(b) && b >= 0.0)) bad += 1.0;
+        smu += a;
+        snu += b;
+        xmu = fmax(xmu, a);
+        xnu = fmax(xnu, b);
+        nmu = fmin(nmu, a);
+        nnu = fmin(nnu, b);
+    }
+    const double r0 = block_reduce<R_SUM>(smu, sh);
+    const double r1 = block_reduce<R_SUM>(snu, sh);
+    const double r2 = block_reduce<R_MAX>(xmu, sh);
+    const double r3 = block_reduce<R_MAX>(xnu, sh);
+    const double r4 = block_reduce<R_MIN>(nmu, sh);
+    const double r5 = block_reduce<R_MIN>(nnu, sh);
+    const double r6 = block_reduce<R_SUM>(bad, sh);
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.x;
+        partials[S_SUM_MU * kMaxRedBlocks + b] = r0;
+        partials[S_SUM_NU * kMaxRedBlocks + b] = r1;
+        partials[S_MAX_MU * kMaxRedBlocks + b] = r2;
+        partials[S_MAX_NU * kMaxRedBlocks + b] = r3;
+        partials[S_MIN_MU * kMaxRedBlocks + b] = r4;
+        partials[S_MIN_NU * kMaxRedBlocks + b] = r5;
+        partials[S_BAD * kMaxRedBlocks + b] = r6;
+    }
+}
+
+template <typename T>
+hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, int nblocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL((stats_kernel<T>), dim3(nblocks), dim3(kRedBlock), 0, stream, mu, nu, N, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void fill_kernel(T *x, long long N, T value)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] = value;
+}
+
+template <typename T>
+hipError_t launch_fill(T *x, long long N, T value, hipStream_t stream)
+{
+    const long long b = (N + 255) / 256;
+    hipLaunchKernelGGL((fill_kernel<T>), dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, stream, x, N,
+                       value);
+    return hipGetLastError();
+}
+
+// out = mul * (in + sign * (*shift)) for up to two fields; a null shift adds 0.
+template <typename T>
+__global__ void shift_scale_kernel(T *out_a, const T *in_a, const double *shift_a, double sign_a, T *out_b,
+                                   const T *in_b, const double *shift_b, double sign_b, long long N, double mul)
+{
+    const T ca = shift_a != nullptr ? T(sign_a * *shift_a) : T(0);
+    const T cb = shift_b != nullptr ? T(sign_b * *shift_b) : T(0);
+    const T m = T(mul);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (out_a != nullptr) out_a[i] = m * (in_a[i] + ca);
+        if (out_b != nullptr) out_b[i] = m * (in_b[i] + cb);
+    }
+}
+
+template <typename T>
+hipError_t launch_shift_scale(T *out_a, const T *in_a, const double *shift_a, double sign_a, T *out_b,
+                              const T *in_b, const double *shift_b, double sign_b, long long N, double mul,
+                              hipStream_t stream)
+{
+    const long long b = (N + 255) / 256;
+    hipLaunchKernelGGL((shift_scale_kernel<T>), dim3((unsigned)(b < 8192 ? b : 8192)), dim3(256), 0, stream,
+                       out_a, in_a, shift_a, sign_a, out_b, in_b, shift_b, sign_b, N, mul);
+    return hipGetLastError();
+}
+
+__device__ double slot_reduce_sum(const double *partials, int slot, int nb, double *sh)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[slot * kMaxRedBlocks + i];
+    return block_reduce<R_SUM>(v, sh);
+}
+__device__ double slot_reduce_max(const double *partials, int slot, int nb, double *sh)
+{
+    double v = -INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, partials[slot * kMaxRedBlocks + i]);
+    return block_reduce<R_MAX>(v, sh);
+}
+__device__ double slot_reduce_min(const double *partials, int slot, int nb, double *sh)
+{
+    double v = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmin(v, partials[slot * kMaxRedBlocks + i]);
+    return block_reduce<R_MIN>(v, sh);
+}
+
+__device__ double step_rule(double sigma, double increase, double G, const CtrlParams &p)
+{
+    if (increase < p.beta1 * sigma * G) return fmax(p.alpha2 * sigma, p.sigma_min);
+    if (increase > p.beta2 * sigma * G) return p.alpha1 * sigma;
+    return sigma;
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, int mode, CtrlParams prm, TraceRec *trace)
+{
+    __shared__ double sh[kRedBlock / kWave];
+    if (mode == CTRL_INIT) {
+        const double smu = slot_reduce_sum(partials, S_SUM_MU, nb, sh);
+        const double snu = slot_reduce_sum(partials, S_SUM_NU, nb, sh);
+        const double xmu = slot_reduce_max(partials, S_MAX_MU, nb, sh);
+        const double xnu = slot_reduce_max(partials, S_MAX_NU, nb, sh);
+        const double nmu = slot_reduce_min(partials, S_MIN_MU, nb, sh);
+        const double nnu = slot_reduce_min(partials, S_MIN_NU, nb, sh);
+        const double bad = slot_reduce_sum(partials, S_BAD, nb, sh);
+        if (threadIdx.x == 0) {
+            st->mass_mu = prm.vol * smu;
+            st->mass_nu = prm.vol * snu;
+            st->max_mu = xmu;
+            st->max_nu = xnu;
+            st->min_mu = nmu;
+            st->min_nu = nnu;
+            st->bad = bad;
+            st->sigma = prm.sigma0 > 0.0 ? prm.sigma0 : 8.0 * fmin(1.0 / xmu, 1.0 / xnu);
+            st->J_old = st->P = st->G = st->J_new = st->gap = 0.0;
+            st->dual_head = st->primal_head = st->G_head = 0.0;
+            st->mean_a = st->mean_b = 0.0;
+            st->iter = 0;
+            st->done = 0;
+            st->nonfinite = 0;
+            st->ntrace = 0;
+        }
+        return;
+    }
+    if (mode == CTRL_MEANS) {
+        const double a = slot_reduce_sum(partials, S_MEAN_A, nb, sh);
+        const double b = slot_reduce_sum(partials, S_MEAN_B, nb, sh);
+        if (threadIdx.x == 0) {
+            st->mean_a = a * prm.inv_N;
+            st->mean_b = b * prm.inv_N;
+        }
+        return;
+    }
+    if (st->done) return;
+    if (mode == CTRL_HEAD_PHI || mode == CTRL_HEAD_PSI) {
+        const double a = slot_reduce_sum(partials, S_P_TGT, nb, sh);
+        const double b = slot_reduce_sum(partials, S_PC_SRC, nb, sh);
+        const double P = slot_reduce_sum(partials, S_PRIMAL, nb, sh);
+        const double G = slot_reduce_sum(partials, S_G, nb, sh);
+        if (threadIdx.x == 0) {
+            st->J_old = prm.vol * (a + b);
+            st->P = prm.vol * P;
+            st->G = prm.vol * G;
+            if (!(isfinite(st->J_old) && isfinite(st->G) && isfinite(st->P))) {
+                st->nonfinite = 1;
+                st->done = 1;
+                return;
+            }
+            if (mode == CTRL_HEAD_PHI) {
+                st->gap = fmax(fabs(st->P - st->J_old), st->G);
+                st->dual_head = st->J_old;
+                st->primal_head = st->P;
+                st->G_head = st->G;
+                if (st->ntrace < kMaxTrace) {
+                    TraceRec &r = trace[st->ntrace];
+                    r.iter = st->iter;
+                    r.dual = st->J_old;
+                    r.primal = st->P;
+                    r.G = st->G;
+                    r.gap = st->gap;
+                    r.sigma = st->sigma;
+                    r.J_half = NAN;
+                    r.I_new = NAN;
+                }
+                st->ntrace += 1;
+                if (prm.tol > 0.0 && st->gap < prm.tol) st->done = 1;
+            }
+        }
+        return;
+    }
+    if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
+        const double a = slot_reduce_sum(partials, S_Q_TGT, nb, sh);
+        const double b = slot_reduce_sum(partials, S_Q_SRC, nb, sh);
+        if (threadIdx.x == 0) {
+            st->J_new = prm.vol * (a + b);
+            if (!isfinite(st->J_new)) {
+                st->nonfinite = 1;
+                st->done = 1;
+                return;
+            }
+            const int tr = st->ntrace - 1;
+            if (tr >= 0 && tr < kMaxTrace) {
+                if (mode == CTRL_STEP_PHI)
+                    trace[tr].J_half = st->J_new;
+                else
+                    trace[tr].I_new = st->J_new;
+            }
+            st->sigma = step_rule(st->sigma, st->J_new - st->J_old, st->G, prm);
+            if (mode == CTRL_STEP_PSI) st->iter += 1;
+        }
+    }
+}
+
+hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, int mode, CtrlParams prm,
+                       TraceRec *trace, hipStream_t stream)
+{
+    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(kRedBlock), 0, stream, st, partials, nblocks, mode, prm, trace);
+    return hipGetLastError();
+}
+
+#define BFM_INST_RED(T)                                                                                      \
+    template hipError_t launch_dot2<T>(const T *, const T *, const T *, const T *, long long, double *,      \
+                                       double *, int, const int32_t *, hipStream_t);                         \
+    template hipError_t launch_stats<T>(const T *, const T *, long long, double *, int, hipStream_t);        \
+    template hipError_t launch_fill<T>(T *, long long, T, hipStream_t);                                      \
+    template hipError_t launch_shift_scale<T>(T *, const T *, const double *, double, T *, const T *,       \
+                                              const double *, double, long long, double, hipStream_t);
+BFM_INST_RED(float)
+BFM_INST_RED(double)
+
+}  // namespace bfm

@@ -1,0 +1,572 @@
+// Host side of the C ABI: parameter validation, plans, workspace layout,
+// spectral tables and the back-and-forth loop (Algorithm 1) enqueued on a
+// HIP stream, with the step-size state kept on the device.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace bfm;
+
+// ----------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+static bfm_status fail(bfm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail(BFM_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                  \
+    } while (0)
+
+extern "C" const char *bfm_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *bfm_version(void) { return "bfm-gfx950 0.1"; }
+
+// ------------------------------------------------------------------ plan
+
+struct bfm_plan_s {
+    bfm_params prm;
+    Grid g;
+    size_t esz;
+    AxisPlan ax[3];
+    int red_blocks;
+    // workspace layout (byte offsets from the workspace base)
+    size_t off_state, off_trace, off_part, off_tables, off_pc, off_rho, off_f, total;
+    size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
+    std::vector<unsigned char> tables;         // host image of the spectral tables
+};
+
+static bool is_2a3b(int n)
+{
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool factor_radices(int n, uint32_t *code, int *nstages)
+{
+    int s = 0;
+    uint32_t c = 0;
+    while (n % 4 == 0) { c |= 0u << (2 * s); ++s; n /= 4; }
+    while (n % 2 == 0) { c |= 2u << (2 * s); ++s; n /= 2; }
+    while (n % 3 == 0) { c |= 3u << (2 * s); ++s; n /= 3; }
+    if (n != 1 || s > 16) return false;
+    *code = c;
+    *nstages = s;
+    return true;
+}
+
+static bfm_status check_params(const bfm_params *p)
+{
+    if (p == nullptr) return fail(BFM_EINVAL, "params is NULL");
+    if (p->ndim != 2 && p->ndim != 3) return fail(BFM_EINVAL, "ndim must be 2 or 3 (got %d)", p->ndim);
+    for (int a = 0; a < p->ndim; ++a) {
+        const int n = p->shape[a];
+        if (n < 4 || n > 4096 || !is_2a3b(n))
+            return fail(BFM_EINVAL, "shape[%d] = %d: need 4 <= n <= 4096 and n = 2^a 3^b", a, n);
+    }
+    if (p->dtype != BFM_F32 && p->dtype != BFM_F64) return fail(BFM_EINVAL, "dtype must be BFM_F32 or BFM_F64");
+    if (p->max_iters < 0) return fail(BFM_EINVAL, "max_iters must be >= 0");
+    if (!(p->tol >= 0.0) || !isfinite(p->tol)) return fail(BFM_EINVAL, "tol must be finite and >= 0");
+    if (!isfinite(p->sigma0)) return fail(BFM_EINVAL, "sigma0 must be finite");
+    if (!(p->sigma_min > 0.0) || !isfinite(p->sigma_min)) return fail(BFM_EINVAL, "sigma_min must be > 0");
+    if (!(0.0 < p->beta1 && p->beta1 < p->beta2 && p->beta2 < 1.0))
+        return fail(BFM_EINVAL, "need 0 < beta1 < beta2 < 1");
+    if (!(p->alpha1 > 1.0 && p->alpha2 > 0.0 && p->alpha2 < 1.0) || !isfinite(p->alpha1))
+        return fail(BFM_EINVAL, "need alpha1 > 1 and 0 < alpha2 < 1");
+    if (p->check_every < 1) return fail(BFM_EINVAL, "check_every must be >= 1");
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_params_init(bfm_params *p, int32_t ndim, const int32_t *shape, int32_t dtype)
+{
+    if (p == nullptr || shape == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    memset(p, 0, sizeof(*p));
+    p->ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) p->shape[a] = shape[a];
+    p->dtype = dtype;
+    p->max_iters = 60;
+    p->tol = 0.0;
+    p->sigma0 = 0.0;
+    p->sigma_min = 0.01;
+    p->beta1 = 0.25;
+    p->beta2 = 0.75;
+    p->alpha1 = 1.25;
+    p->alpha2 = 0.8;
+    p->check_every = 8;
+    return check_params(p);
+}
+
+template <typename T>
+static void put(std::vector<unsigned char> &img, size_t off, T v) { memcpy(img.data() + off, &v, sizeof(T)); }
+
+static void build_tables(bfm_plan_s *P)
+{
+    const int d = P->g.ndim;
+    const bool f64 = P->prm.dtype == BFM_F64;
+    const size_t ce = 2 * P->esz;   // complex element
+    size_t off = 0;
+    for (int a = 0; a < d; ++a) {
+        const int n = P->g.n[a];
+        P->tab_tw[a] = off;  off = align256(off + (size_t)n * ce);
+        P->tab_qw[a] = off;  off = align256(off + (size_t)n * ce);
+        P->tab_lam[a] = off; off = align256(off + (size_t)n * P->esz);
+    }
+    P->tables.assign(off, 0);
+    for (int a = 0; a < d; ++a) {
+        const int n = P->g.n[a];
+        for (int j = 0; j < n; ++j) {
+            const double th = 2.0 * M_PI * (double)j / (double)n;     // exp(-2 pi i j / n)
+            const double ph = M_PI * (double)j / (2.0 * (double)n);   // exp(-i pi j / (2n))
+            const double s = sin(ph);
+            const double lam = 4.0 * s * s * (double)n * (double)n;   // 4 sin^2(pi k/(2n)) n^2
+            if (f64) {
+                put<double>(P->tables, P->tab_tw[a] + j * ce, cos(th));
+                put<double>(P->tables, P->tab_tw[a] + j * ce + 8, -sin(th));
+                put<double>(P->tables, P->tab_qw[a] + j * ce, cos(ph));
+                put<double>(P->tables, P->tab_qw[a] + j * ce + 8, -sin(ph));
+                put<double>(P->tables, P->tab_lam[a] + j * 8, lam);
+            } else {
+                put<float>(P->tables, P->tab_tw[a] + j * ce, (float)cos(th));
+                put<float>(P->tables, P->tab_tw[a] + j * ce + 4, (float)-sin(th));
+                put<float>(P->tables, P->tab_qw[a] + j * ce, (float)cos(ph));
+                put<float>(P->tables, P->tab_qw[a] + j * ce + 4, (float)-sin(ph));
+                put<float>(P->tables, P->tab_lam[a] + j * 4, (float)lam);
+            }
+        }
+    }
+}
+
+extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
+{
+    if (out == nullptr) return fail(BFM_EINVAL, "out is NULL");
+    *out = nullptr;
+    bfm_status s = check_params(p);
+    if (s != BFM_OK) return s;
+    bfm_plan_s *P = new (std::nothrow) bfm_plan_s();
+    if (P == nullptr) return fail(BFM_EINVAL, "out of host memory");
+    P->prm = *p;
+    P->esz = p->dtype == BFM_F64 ? 8 : 4;
+    Grid &g = P->g;
+    g.ndim = p->ndim;
+    g.N = 1;
+    for (int a = 0; a < 3; ++a) g.n[a] = a < p->ndim ? p->shape[a] : 1;
+    for (int a = p->ndim - 1; a >= 0; --a) {
+        g.stride[a] = g.N;
+        g.N *= g.n[a];
+    }
+    for (int a = p->ndim; a < 3; ++a) g.stride[a] = 0;
+    g.vol = 1.0;
+    for (int a = 0; a < p->ndim; ++a) g.vol /= g.n[a];
+    for (int a = 0; a < p->ndim; ++a) {
+        AxisPlan &ap = P->ax[a];
+        ap.n = g.n[a];
+        ap.inner = (int)g.stride[a];
+        if (!factor_radices(ap.n, &ap.radices, &ap.nstages)) {
+            delete P;
+            return fail(BFM_EINVAL, "axis %d: size %d has no radix-2/3/4 factorisation", a, ap.n);
+        }
+    }
+    long long rb = (g.N + kRedBlock - 1) / kRedBlock;
+    P->red_blocks = (int)(rb < kMaxRedBlocks ? rb : kMaxRedBlocks);
+    build_tables(P);
+    size_t off = 0;
+    P->off_state = off;  off = align256(off + sizeof(DevState));
+    P->off_trace = off;  off = align256(off + sizeof(TraceRec) * kMaxTrace);
+    P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * kMaxRedBlocks);
+    P->off_tables = off; off = align256(off + P->tables.size());
+    const size_t fb = align256((size_t)g.N * P->esz);
+    P->off_pc = off;  off += fb;
+    P->off_rho = off; off += fb;
+    P->off_f = off;   off += fb;
+    P->total = off;
+    *out = P;
+    return BFM_OK;
+}
+
+extern "C" void bfm_plan_destroy(bfm_plan plan) { delete plan; }
+
+extern "C" bfm_status bfm_plan_workspace_bytes(bfm_plan plan, size_t *bytes)
+{
+    if (plan == nullptr || bytes == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    *bytes = plan->total;
+    return BFM_OK;
+}
+
+// ------------------------------------------------------- device pointers
+
+struct Ws {
+    DevState *st;
+    TraceRec *trace;
+    double *part;
+    unsigned char *tables;
+    void *pc, *rho, *f;
+    double *slot(int s) const { return part + (size_t)s * kMaxRedBlocks; }
+};
+
+static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
+{
+    if (ws == nullptr) return fail(BFM_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(BFM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < P->total)
+        return fail(BFM_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, P->total);
+    unsigned char *b = (unsigned char *)ws;
+    w->st = (DevState *)(b + P->off_state);
+    w->trace = (TraceRec *)(b + P->off_trace);
+    w->part = (double *)(b + P->off_part);
+    w->tables = b + P->off_tables;
+    w->pc = b + P->off_pc;
+    w->rho = b + P->off_rho;
+    w->f = b + P->off_f;
+    return BFM_OK;
+}
+
+static hipError_t upload_tables(bfm_plan P, const Ws &w, hipStream_t s)
+{
+    return hipMemcpyAsync(w.tables, P->tables.data(), P->tables.size(), hipMemcpyHostToDevice, s);
+}
+
+static CtrlParams ctrl_params(bfm_plan P)
+{
+    CtrlParams c;
+    c.tol = P->prm.tol;
+    c.sigma0 = P->prm.sigma0;
+    c.sigma_min = P->prm.sigma_min;
+    c.beta1 = P->prm.beta1;
+    c.beta2 = P->prm.beta2;
+    c.alpha1 = P->prm.alpha1;
+    c.alpha2 = P->prm.alpha2;
+    c.vol = P->g.vol;
+    c.inv_N = 1.0 / (double)P->g.N;
+    return c;
+}
+
+// Poisson solve of f = a - b (b may be null) into `g_out`, G partials into
+// slot S_G.  With `update` non-null the last inverse pass writes
+// update = update + sigma * g instead of storing g.  The forward passes run
+// unconditionally of `done`; the inverse passes and the update are skipped
+// once the device stop flag is set (they run after the head controller).
+template <typename T>
+static hipError_t poisson_forward(bfm_plan P, const Ws &w, const T *a, T *b, int zero_b, T *F,
+                                  const int32_t *done, hipStream_t s)
+{
+    const Grid &g = P->g;
+    const int d = g.ndim;
+    hipError_t e;
+    for (int ax = d - 1; ax >= 0; --ax) {
+        const T *src = ax == d - 1 ? a : F;
+        T *sub = ax == d - 1 ? b : nullptr;
+        e = launch_dct2_axis<T>(src, sub, F, P->ax[ax], g.N, ax == d - 1 ? zero_b : 0,
+                                w.tables + P->tab_tw[ax], w.tables + P->tab_qw[ax], done, s);
+        if (e != hipSuccess) return e;
+    }
+    const T *l0 = (const T *)(w.tables + P->tab_lam[0]);
+    const T *l1 = (const T *)(w.tables + P->tab_lam[d > 1 ? 1 : 0]);
+    const T *l2 = (const T *)(w.tables + P->tab_lam[d > 2 ? 2 : 0]);
+    return launch_spectral_divide<T>(F, g, l0, l1, l2, w.slot(S_G), P->red_blocks, done, s);
+}
+
+template <typename T>
+static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *update, const int32_t *done,
+                                  hipStream_t s)
+{
+    const Grid &g = P->g;
+    const int d = g.ndim;
+    hipError_t e;
+    for (int ax = 0; ax < d; ++ax) {
+        const bool last = ax == d - 1;
+        T *dst = last ? (update != nullptr ? update : out) : F;
+        e = launch_dct3_axis<T>(F, dst, last ? update : nullptr, last && update ? &w.st->sigma : nullptr,
+                                P->ax[ax], g.N, w.tables + P->tab_tw[ax], w.tables + P->tab_qw[ax], done, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One half-step of Algorithm 1 on J(p) = <p, tgt> + <p^c, src>:
+//   head:  pc = p^c, J(p), map + pushforward rho = T#src, primal cost,
+//          H^1 gradient g of tgt - rho and G; controller `head_mode`;
+//   step:  p <- p + sigma g, q = p^c, J(p), controller `step_mode`.
+template <typename T>
+static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T *tgt, T *q, int head_mode,
+                            int step_mode, bool head_only, hipStream_t s)
+{
+    const Grid &g = P->g;
+    const int32_t *done = &w.st->done;
+    const int nb = P->red_blocks;
+    T *pc = (T *)w.pc, *rho = (T *)w.rho, *F = (T *)w.f;
+    const CtrlParams cp = ctrl_params(P);
+    hipError_t e;
+    if ((e = ctransform_field<T>(g, p, pc, done, s)) != hipSuccess) return e;
+    if ((e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
+        return e;
+    if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, done, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = poisson_forward<T>(P, w, tgt, rho, 1, F, done, s)) != hipSuccess) return e;
+    if ((e = launch_ctrl(w.st, w.part, nb, head_mode, cp, w.trace, s)) != hipSuccess) return e;
+    if (head_only) return hipSuccess;
+    if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
+    if ((e = ctransform_field<T>(g, p, q, done, s)) != hipSuccess) return e;
+    if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
+        return e;
+    return launch_ctrl(w.st, w.part, nb, step_mode, cp, w.trace, s);
+}
+
+template <typename T>
+static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_init, T *phi, T *psi, T *Tmap,
+                             const Ws &w, hipStream_t s, bfm_result *res)
+{
+    const Grid &g = P->g;
+    const int nb = P->red_blocks;
+    const CtrlParams cp = ctrl_params(P);
+    DevState hs;
+    HIP_TRY(upload_tables(P, w, s));
+    HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, nb, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_INIT, cp, w.trace, s));
+    HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.bad > 0) return fail(BFM_EINVAL, "mu/nu contain %.0f negative or non-finite values", hs.bad);
+    if (fabs(hs.mass_mu - 1.0) > 1e-5 || fabs(hs.mass_nu - 1.0) > 1e-5)
+        return fail(BFM_EINVAL, "densities must have unit mass (cell_volume*sum): mu %.9g, nu %.9g", hs.mass_mu,
+                    hs.mass_nu);
+    if (!(hs.max_mu > 0.0) || !(hs.max_nu > 0.0)) return fail(BFM_EINVAL, "a density is identically zero");
+
+    HIP_TRY(launch_fill<T>((T *)w.rho, g.N, T(0), s));
+    if (phi_init != nullptr)
+        HIP_TRY(hipMemcpyAsync(phi, phi_init, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    else
+        HIP_TRY(launch_fill<T>(phi, g.N, T(0), s));
+
+    const int K = P->prm.check_every;
+    for (int it = 0; it <= P->prm.max_iters; ++it) {
+        const bool last = it == P->prm.max_iters;
+        HIP_TRY(half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, last, s));
+        if (last) break;
+        HIP_TRY(half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, s));
+        if ((it + 1) % K == 0) {
+            HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hs.done) break;
+        }
+    }
+    // final outputs: T from the last head's phi^c, phi - mean, psi = phi^c + mean
+    T *pc = (T *)w.pc;
+    if (Tmap != nullptr)
+        HIP_TRY(launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s));
+    HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
+    HIP_TRY(launch_dot2<T>(pc, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_MEANS, cp, w.trace, s));
+    HIP_TRY(launch_shift_scale<T>(phi, phi, &w.st->mean_a, -1.0, psi, pc, &w.st->mean_a, 1.0, g.N, 1.0, s));
+    HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (res != nullptr) {
+        memset(res, 0, sizeof(*res));
+        res->iters = hs.iter;
+        res->converged = (hs.done && !hs.nonfinite) ? 1 : 0;
+        res->status = hs.nonfinite ? BFM_ENUMERIC : BFM_OK;
+        res->dual = hs.dual_head;
+        res->primal = hs.primal_head;
+        res->gap = hs.gap;
+        res->G = hs.G_head;
+        res->sigma = hs.sigma;
+        res->mass_mu = hs.mass_mu;
+        res->mass_nu = hs.mass_nu;
+    }
+    if (hs.nonfinite) return fail(BFM_ENUMERIC, "non-finite value in the dual, primal or gradient norm");
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *phi_init, void *phi,
+                                void *psi, void *T, void *workspace, size_t ws_bytes, void *stream,
+                                bfm_result *result)
+{
+    if (plan == nullptr) return fail(BFM_EINVAL, "plan is NULL");
+    if (mu == nullptr || nu == nullptr || phi == nullptr || psi == nullptr)
+        return fail(BFM_EINVAL, "mu, nu, phi and psi must be non-NULL");
+    if (phi == psi || phi == mu || phi == nu || psi == mu || psi == nu)
+        return fail(BFM_EINVAL, "phi and psi must be distinct buffers, distinct from mu and nu");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return solve_impl<double>(plan, (const double *)mu, (const double *)nu, (const double *)phi_init,
+                                  (double *)phi, (double *)psi, (double *)T, w, s, result);
+    return solve_impl<float>(plan, (const float *)mu, (const float *)nu, (const float *)phi_init, (float *)phi,
+                             (float *)psi, (float *)T, w, s, result);
+}
+
+// ------------------------------------------------------------ primitives
+
+extern "C" bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, void *workspace, size_t ws_bytes,
+                                     void *stream)
+{
+    if (plan == nullptr || in == nullptr || out == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        HIP_TRY(ctransform_field<double>(plan->g, (const double *)in, (double *)out, nullptr, s));
+    else
+        HIP_TRY(ctransform_field<float>(plan->g, (const float *)in, (float *)out, nullptr, s));
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t sign, const void *in, void *out,
+                                          void *stream)
+{
+    if (plan == nullptr || in == nullptr || out == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    if (axis < 0 || axis >= plan->g.ndim) return fail(BFM_EINVAL, "axis %d out of range", axis);
+    if (sign != 1 && sign != -1) return fail(BFM_EINVAL, "sign must be +1 or -1");
+    const Grid &g = plan->g;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = g.n[axis], inner = (int)g.stride[axis];
+    if (plan->prm.dtype == BFM_F64)
+        HIP_TRY(launch_ct_axis<double>((const double *)in, (double *)out, n, inner, g.N / n, (double)sign, nullptr,
+                                       s));
+    else
+        HIP_TRY(launch_ct_axis<float>((const float *)in, (float *)out, n, inner, g.N / n, (float)sign, nullptr, s));
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_trace(bfm_plan plan, const void *workspace, size_t ws_bytes, double *host,
+                                int32_t max_records, int32_t *count, void *stream)
+{
+    if (plan == nullptr || count == nullptr || (host == nullptr && max_records > 0))
+        return fail(BFM_EINVAL, "NULL argument");
+    Ws w;
+    bfm_status st = check_ws(plan, (void *)workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    DevState hs;
+    HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *count = hs.ntrace;
+    int m = hs.ntrace < max_records ? hs.ntrace : max_records;
+    if (m > kMaxTrace) m = kMaxTrace;
+    if (m > 0) {
+        HIP_TRY(hipMemcpyAsync(host, w.trace, (size_t)m * sizeof(TraceRec), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return BFM_OK;
+}
+
+static double host_slot_sum(const std::vector<double> &v) {
+    double acc = 0.0;
+    for (double x : v) acc += x;
+    return acc;
+}
+
+template <typename T>
+static bfm_status push_impl(bfm_plan P, const T *phic, const T *mass, T *rho, T *Tmap, double *primal,
+                            const Ws &w, hipStream_t s)
+{
+    const int nb = P->red_blocks;
+    HIP_TRY(launch_fill<T>(rho, P->g.N, T(0), s));
+    HIP_TRY(launch_splat<T>(P->g, phic, mass, rho, Tmap, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, nullptr, s));
+    if (primal != nullptr) {
+        std::vector<double> h(nb);
+        HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_PRIMAL), nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *primal = P->g.vol * host_slot_sum(h);
+    }
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_pushforward(bfm_plan plan, const void *phic, const void *mass, void *rho, void *T,
+                                      double *primal, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || phic == nullptr || mass == nullptr || rho == nullptr)
+        return fail(BFM_EINVAL, "NULL argument");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return push_impl<double>(plan, (const double *)phic, (const double *)mass, (double *)rho, (double *)T,
+                                 primal, w, s);
+    return push_impl<float>(plan, (const float *)phic, (const float *)mass, (float *)rho, (float *)T, primal, w,
+                            s);
+}
+
+template <typename T>
+static bfm_status poisson_impl(bfm_plan P, const T *f, T *g, double *G, const Ws &w, hipStream_t s)
+{
+    const int nb = P->red_blocks;
+    HIP_TRY(upload_tables(P, w, s));
+    HIP_TRY(poisson_forward<T>(P, w, f, nullptr, 0, g, nullptr, s));
+    HIP_TRY(poisson_inverse<T>(P, w, g, g, nullptr, nullptr, s));
+    if (G != nullptr) {
+        std::vector<double> h(nb);
+        HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_G), nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *G = P->g.vol * host_slot_sum(h);
+    }
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_poisson_neumann(bfm_plan plan, const void *f, void *g, double *G, void *workspace,
+                                          size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || f == nullptr || g == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return poisson_impl<double>(plan, (const double *)f, (double *)g, G, w, s);
+    return poisson_impl<float>(plan, (const float *)f, (float *)g, G, w, s);
+}
+
+template <typename T>
+static bfm_status grad_impl(bfm_plan P, const T *phi, const T *psi, double scale, T *gmu, T *gnu, const Ws &w,
+                            hipStream_t s)
+{
+    const int nb = P->red_blocks;
+    HIP_TRY(launch_dot2<T>(psi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
+    HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_MEANS, ctrl_params(P), w.trace, s));
+    HIP_TRY(launch_shift_scale<T>(gmu, psi, &w.st->mean_a, -1.0, gnu, phi, &w.st->mean_b, -1.0, P->g.N,
+                                  2.0 * P->g.vol * scale, s));
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_grad(bfm_plan plan, const void *phi, const void *psi, double scale, void *grad_mu,
+                               void *grad_nu, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || phi == nullptr || psi == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    if (!isfinite(scale)) return fail(BFM_EINVAL, "scale must be finite");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return grad_impl<double>(plan, (const double *)phi, (const double *)psi, scale, (double *)grad_mu,
+                                 (double *)grad_nu, w, s);
+    return grad_impl<float>(plan, (const float *)phi, (const float *)psi, scale, (float *)grad_mu,
+                            (float *)grad_nu, w, s);
+}

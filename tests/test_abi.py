@@ -1,0 +1,109 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and host-side validation rejects bad arguments before any
+device call (include/bfm.h)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_12154_amd import bfm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfm.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bfm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = bfm.lib()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(bfm.EXPORTED)
+    assert L.bfm_version().decode().startswith("bfm-gfx950")
+
+
+def _params(shape, dtype=bfm.BFM_F32):
+    p = bfm.Params()
+    shp = (ctypes.c_int32 * 3)(*(list(shape) + [1] * (3 - len(shape))))
+    st = bfm.lib().bfm_params_init(ctypes.byref(p), len(shape), shp, dtype)
+    return st, p
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (384, 1024), (4096, 4096), (96, 48, 64), (4, 6)])
+def test_params_defaults_are_paper_constants(shape):
+    st, p = _params(shape)
+    assert st == bfm.BFM_OK
+    assert (p.sigma_min, p.beta1, p.beta2, p.alpha1, p.alpha2) == (0.01, 0.25, 0.75, 1.25, 0.8)
+    assert p.sigma0 == 0.0 and p.tol == 0.0
+
+
+@pytest.mark.parametrize("shape", [(5, 8), (64, 8192), (2, 64), (64,), (7, 7, 7), (64, 64, 64, 64)])
+def test_bad_shapes_rejected(shape):
+    if len(shape) in (1, 4):
+        p = bfm.Params()
+        shp = (ctypes.c_int32 * 3)(64, 64, 64)
+        st = bfm.lib().bfm_params_init(ctypes.byref(p), len(shape), shp, 0)
+    else:
+        st, p = _params(shape)
+    assert st == bfm.BFM_EINVAL
+    assert "n" in bfm.lib().bfm_last_error().decode()
+    h = ctypes.c_void_p()
+    assert bfm.lib().bfm_plan_create(ctypes.byref(p), ctypes.byref(h)) == bfm.BFM_EINVAL
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("dtype", 7), ("beta1", 0.9), ("alpha1", 0.5), ("alpha2", 1.5),
+                                         ("sigma_min", 0.0), ("tol", -1.0), ("check_every", 0),
+                                         ("max_iters", -3), ("sigma0", float("nan"))])
+def test_bad_parameters_rejected(field, value):
+    st, p = _params((32, 32))
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    assert bfm.lib().bfm_plan_create(ctypes.byref(p), ctypes.byref(h)) == bfm.BFM_EINVAL
+    assert bfm.lib().bfm_last_error().decode()
+
+
+def test_workspace_size_and_errors_before_launch():
+    plan = bfm.Plan((64, 48), dtype="float64")
+    assert plan.ws_bytes >= 3 * 64 * 48 * 8
+    L = bfm.lib()
+    res = bfm.Result()
+    dummy = ctypes.c_void_p(0x1000)
+    mu, nu, phi, psi = (ctypes.c_void_p(a) for a in (0x1000, 0x1100, 0x1200, 0x1300))
+    # null workspace -> EWORKSPACE (validated before any device call)
+    st = L.bfm_solve(plan.handle, mu, nu, None, phi, psi, None, None, plan.ws_bytes, None, ctypes.byref(res))
+    assert st == bfm.BFM_EWORKSPACE
+    # misaligned
+    st = L.bfm_solve(plan.handle, mu, nu, None, phi, psi, None, ctypes.c_void_p(0x1010), plan.ws_bytes, None,
+                     ctypes.byref(res))
+    assert st == bfm.BFM_EWORKSPACE
+    # too small
+    st = L.bfm_solve(plan.handle, mu, nu, None, phi, psi, None, ctypes.c_void_p(0x10000), plan.ws_bytes - 1, None,
+                     ctypes.byref(res))
+    assert st == bfm.BFM_EWORKSPACE
+    # null densities / aliased outputs -> EINVAL
+    assert L.bfm_solve(plan.handle, None, nu, None, phi, psi, None, ctypes.c_void_p(0x10000), plan.ws_bytes,
+                       None, ctypes.byref(res)) == bfm.BFM_EINVAL
+    assert L.bfm_solve(plan.handle, mu, nu, None, phi, phi, None, ctypes.c_void_p(0x10000), plan.ws_bytes,
+                       None, ctypes.byref(res)) == bfm.BFM_EINVAL
+    assert L.bfm_solve(None, dummy, dummy, None, dummy, dummy, None, None, 0, None, None) == bfm.BFM_EINVAL
+    assert L.bfm_ctransform(plan.handle, None, dummy, None, 0, None) == bfm.BFM_EINVAL
+    assert L.bfm_grad(plan.handle, dummy, dummy, float("inf"), None, None, ctypes.c_void_p(0x10000),
+                      plan.ws_bytes, None) == bfm.BFM_EINVAL
+    L.bfm_plan_workspace_bytes(None, None)
+    assert "NULL" in L.bfm_last_error().decode()
+
+
+def test_plan_python_validation():
+    plan = bfm.Plan((32, 32))
+    with pytest.raises(TypeError):
+        plan.ctransform(__import__("torch").zeros(32, 32))
+    with pytest.raises(bfm.BFMError):
+        bfm.Plan((31, 32))
