@@ -39,13 +39,15 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_times(plan, mu, nu, reps):
+def kernel_times(plan, phi, reps):
     """Average duration (ms) of each hot kernel class, HIP events on the
-    stream the library launches on (the current PyTorch stream)."""
+    stream the library launches on (the current PyTorch stream).  Inputs are
+    what the solver feeds these kernels: the current potential for the first
+    c-transform pass, that pass's output for the second."""
     import torch
-    from paper_1905_12154_amd import bfm  # noqa: F401
     s = torch.cuda.current_stream()
-    f = (mu - nu).contiguous()
+    f = phi.contiguous()
+    a1 = plan.ctransform_axis(f, 1, -1)
     out = torch.empty_like(f)
     res = {}
 
@@ -60,7 +62,7 @@ def kernel_times(plan, mu, nu, reps):
         return a.elapsed_time(b) / reps
 
     res["ct_axis1"] = timeit(lambda: plan.ctransform_axis(f, 1, -1, out=out))
-    res["ct_axis0"] = timeit(lambda: plan.ctransform_axis(f, 0, 1, out=out))
+    res["ct_axis0"] = timeit(lambda: plan.ctransform_axis(a1, 0, 1, out=out))
     return res
 
 
@@ -143,7 +145,7 @@ def main():
     min_gap = min(e["gap"] for e in tr) if tr else float("nan")
 
     # dominant kernel: per-iteration time = launches per iteration x duration
-    kt = kernel_times(plan, mu, nu, args.kernel_reps)
+    kt = kernel_times(plan, r.phi, args.kernel_reps)
     per_iter = {"ct_axis1": 4 * kt["ct_axis1"], "ct_axis0": 4 * kt["ct_axis0"]}
     dom = max(per_iter, key=per_iter.get)
     bytes_per_launch = 2 * N * 4          # read u, write the transformed line (float32)

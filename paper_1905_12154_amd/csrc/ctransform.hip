@@ -12,21 +12,25 @@
 // In index units this is min_j (w_j - i j) + i^2/2 with w_j = j^2/2 + n^2 u_j,
 // i.e. the Legendre transform of the points (j, w_j) at integer slopes i.
 //
-// GPU organisation (one workgroup of 256 lanes handles `lpb` lines, `tpl`
-// lanes per line, C consecutive points per lane):
-//   1. the line is staged in LDS;
+// GPU organisation: a workgroup handles LPB lines with TPL lanes per line and
+// C consecutive points per lane:
+//   1. the lane's C values are loaded into registers (vector loads along
+//      contiguous lines; for strided axes LPB adjacent lines are read as one
+//      vector per grid row) and staged in LDS;
 //   2. each lane builds the lower hull of its own C points (sequential scan,
 //      hull kept as prev/next links in LDS, popped points marked dead);
-//   3. log2(tpl) merge rounds join neighbouring hulls: one lane walks the
+//   3. log2(TPL) merge rounds join neighbouring hulls: one lane walks the
 //      seam (moving the left end left and the right end right until the
 //      joining edge supports both hulls) and relinks;
 //   4. every surviving vertex k, whose hull predecessor is p, is optimal for
 //      the integer slopes i >= (w_k - w_p)/(k - p); it writes k at that start
-//      index (atomic max), and a prefix maximum over i then gives the optimal
-//      vertex of every output (the largest vertex whose range has begun);
+//      index (atomic max), and a prefix maximum over i (wave shuffles) gives
+//      the optimal vertex of every output;
 //   5. the output is re-evaluated directly as (i-k)^2 h^2/2 + u_k.
-// No step depends on the data being convex; ties (collinear points) are
-// removed from the hull, which never changes a minimum value.
+// LDS rows are padded by one slot every 16 entries so that the lane-strided
+// accesses of steps 2, 4 and 5 fall on distinct banks.  No step depends on
+// the data being convex; ties (collinear points) are removed from the hull,
+// which never changes a minimum value.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -34,6 +38,9 @@ namespace bfm {
 
 constexpr short kNone = -1;
 constexpr short kDead = -2;
+
+__device__ __forceinline__ int padi(int j) { return j + (j >> 4); }
+__host__ __device__ inline int padded_len(int n) { return n + (n >> 4) + 1; }
 
 // True when point k is on or above the chord from a to b (a < k < b) in the
 // (j, j^2/2 + n^2 u_j) plane: k can be dropped from the lower hull.
@@ -44,72 +51,123 @@ __device__ __forceinline__ bool above_chord(int a, int k, int b, T ua, T uk, T u
     return q + n2 * r <= T(0);
 }
 
-template <typename T, int C>
-__global__ void __launch_bounds__(256)
-ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines,
-                int tpl, int lpb, T sgn, T h, const int32_t *__restrict__ done)
+// XCD-aware block order: hardware dispatches consecutive block ids round-robin
+// over the 8 XCDs; give each XCD a contiguous range of line groups so that
+// groups sharing cache lines run under the same L2.
+__device__ __forceinline__ long long xcd_block(long long b, long long nb) {
+    const long long q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+template <typename T> struct vec4;
+template <> struct vec4<float> { using type = float4; };
+template <> struct vec4<double> { using type = double4; };
+
+template <typename T, int C, int LPB>
+__global__ void __launch_bounds__(1024)
+ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
+                T sgn, T h, const int32_t *__restrict__ done)
 {
     if (done != nullptr && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *vals = reinterpret_cast<T *>(smem);
-    short *prv = reinterpret_cast<short *>(vals + (size_t)lpb * n);
-    short *nxt = prv + (size_t)lpb * n;
-    int *grp = reinterpret_cast<int *>(nxt + (size_t)lpb * n);   // [lpb][2][tpl]
+    const int NP = padded_len(n);
+    T *vals = reinterpret_cast<T *>(smem);                                   // [LPB][NP]
+    short *links = reinterpret_cast<short *>(vals + (size_t)LPB * NP);        // [LPB][2][NP]
+    int *grp = reinterpret_cast<int *>(links + (size_t)LPB * 2 * NP);        // [LPB][2][tpl]
+    __shared__ int wave_tot[16];
 
     const int tid = threadIdx.x;
-    const long long L0 = (long long)blockIdx.x * lpb;
-    const int tot = lpb * n;
+    const int nthr = blockDim.x;
+    const long long L0 = xcd_block(blockIdx.x, gridDim.x) * LPB;
+    const int l = tid / tpl, t = tid - l * tpl;
+    const long long L = L0 + l;
+    const int j0 = t * C, j1 = min(j0 + C, n);
+    T *v = vals + l * NP;
+    short *pv = links + (size_t)l * 2 * NP;
+    short *nx = pv + NP;
+    int *GH = grp + l * 2 * tpl;
+    int *GT = GH + tpl;
 
+    T u[C];
     // 1. stage the lines (u = sgn * in)
+    const bool in_al = ((uintptr_t)in & 15) == 0, out_al = ((uintptr_t)out & 15) == 0;
     if (inner == 1) {
-        for (int e = tid; e < tot; e += blockDim.x) {
-            const int l = e / n, j = e - l * n;
-            const long long L = L0 + l;
-            vals[e] = L < nlines ? sgn * in[L * n + j] : T(0);
+        const bool vec = (n & 3) == 0 && (C & 3) == 0 && in_al;
+        if (L < nlines && j0 < j1) {
+            const T *src = in + L * n;
+#pragma unroll
+            for (int q = 0; q < C; q += 4) {
+                if (vec && j0 + q + 3 < n) {
+                    const typename vec4<T>::type x = *reinterpret_cast<const typename vec4<T>::type *>(src + j0 + q);
+                    u[q] = x.x; u[q + 1] = x.y; u[q + 2] = x.z; u[q + 3] = x.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) u[q + e] = (q + e < C && j0 + q + e < n) ? src[j0 + q + e] : T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) u[c] = T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            u[c] *= sgn;
+            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
         }
     } else {
-        for (int e = tid; e < tot; e += blockDim.x) {
-            const int l = e % lpb, j = e / lpb;
-            const long long L = L0 + l;
-            vals[l * n + j] = L < nlines ? sgn * in[line_base(L, n, inner) + (long long)j * inner] : T(0);
+        // LPB adjacent lines are adjacent in memory along every grid row
+        const bool vec = LPB == 4 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= nlines && in_al;
+        const long long base0 = line_base(L0, n, inner);
+        if (vec) {
+            for (int j = tid; j < n; j += nthr) {
+                const typename vec4<T>::type x =
+                    *reinterpret_cast<const typename vec4<T>::type *>(in + base0 + (long long)j * inner);
+                const int pj = padi(j);
+                vals[0 * NP + pj] = sgn * x.x;
+                vals[1 * NP + pj] = sgn * x.y;
+                vals[2 * NP + pj] = sgn * x.z;
+                vals[3 * NP + pj] = sgn * x.w;
+            }
+        } else {
+            for (int e = tid; e < LPB * n; e += nthr) {
+                const int ll = e % LPB, j = e / LPB;
+                const long long LL = L0 + ll;
+                vals[ll * NP + padi(j)] = LL < nlines ? sgn * in[line_base(LL, n, inner) + (long long)j * inner] : T(0);
+            }
         }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
     }
     __syncthreads();
 
-    const int l = tid / tpl, t = tid - l * tpl;
-    const T *v = vals + l * n;
-    short *pv = prv + l * n;
-    short *nx = nxt + l * n;
-    int *GH = grp + l * 2 * tpl;
-    int *GT = GH + tpl;
     const T n2 = T(n) * T(n);
-    const int j0 = t * C, j1 = min(j0 + C, n);
-
     // 2. lane-local lower hull of points [j0, j1)
     if (j0 < j1) {
         int top = j0;
-        T utop = v[j0];
-        pv[j0] = kNone;
+        T utop = u[0];
+        pv[padi(j0)] = kNone;
         for (int j = j0 + 1; j < j1; ++j) {
-            const T uj = v[j];
-            int a = pv[top];
+            const T uj = v[padi(j)];
+            int a = pv[padi(top)];
             while (a >= 0) {
-                const T ua = v[a];
+                const T ua = v[padi(a)];
                 if (!above_chord(a, top, j, ua, utop, uj, n2)) break;
-                pv[top] = kDead;
+                pv[padi(top)] = kDead;
                 top = a;
                 utop = ua;
-                a = pv[top];
+                a = pv[padi(top)];
             }
-            pv[j] = (short)top;
+            pv[padi(j)] = (short)top;
             top = j;
             utop = uj;
         }
         int k = top;
-        nx[k] = kNone;
-        while (pv[k] >= 0) {
-            const int p = pv[k];
-            nx[p] = (short)k;
+        nx[padi(k)] = kNone;
+        while (true) {
+            const int p = pv[padi(k)];
+            if (p < 0) break;
+            nx[padi(p)] = (short)k;
             k = p;
         }
         GH[t] = j0;
@@ -130,24 +188,24 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
                     GT[t] = tR;
                 } else {
                     int a = tL, b = hR;
-                    T ua = v[a], ub = v[b];
+                    T ua = v[padi(a)], ub = v[padi(b)];
                     for (;;) {
                         bool moved = false;
-                        const int pa = pv[a];
+                        const int pa = pv[padi(a)];
                         if (pa >= 0) {
-                            const T upa = v[pa];
+                            const T upa = v[padi(pa)];
                             if (above_chord(pa, a, b, upa, ua, ub, n2)) {
-                                pv[a] = kDead;
+                                pv[padi(a)] = kDead;
                                 a = pa;
                                 ua = upa;
                                 moved = true;
                             }
                         }
-                        const int nb = nx[b];
+                        const int nb = nx[padi(b)];
                         if (nb >= 0) {
-                            const T unb = v[nb];
+                            const T unb = v[padi(nb)];
                             if (above_chord(a, b, nb, ua, ub, unb, n2)) {
-                                pv[b] = kDead;
+                                pv[padi(b)] = kDead;
                                 b = nb;
                                 ub = unb;
                                 moved = true;
@@ -155,8 +213,8 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
                         }
                         if (!moved) break;
                     }
-                    nx[a] = (short)b;
-                    pv[b] = (short)a;
+                    nx[padi(a)] = (short)b;
+                    pv[padi(b)] = (short)a;
                     GT[t] = tR;
                 }
             }
@@ -171,11 +229,11 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
         const int j = j0 + c;
         st[c] = n;
         if (j < j1) {
-            const int p = pv[j];
+            const int p = pv[padi(j)];
             if (p == kNone) {
                 st[c] = 0;
             } else if (p >= 0) {
-                T s = T(0.5) * T(j + p) + n2 * (v[j] - v[p]) / T(j - p);
+                T s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) / T(j - p);
                 s = fmin(fmax(s, T(-1)), T(n));
                 const int si = (int)ceil(s);
                 st[c] = si < 0 ? 0 : si;
@@ -183,12 +241,14 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
         }
     }
     __syncthreads();
-    int *mk = reinterpret_cast<int *>(prv) + l * n;   // aliases prv/nxt of this block's lines
-    for (int j = j0; j < j1; ++j) mk[j] = -1;
+    int *mk = reinterpret_cast<int *>(pv);   // NP ints over this line's prev/next links
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c < j1) mk[padi(j0 + c)] = -1;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        if (st[c] < n) atomicMax(&mk[st[c]], j0 + c);
+        if (st[c] < n) atomicMax(&mk[padi(st[c])], j0 + c);
     __syncthreads();
 
     // prefix maximum of the markers along the line
@@ -196,85 +256,159 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
     int m = -1;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int j = j0 + c;
-        if (j < j1) m = max(m, mk[j]);
+        if (j0 + c < j1) m = max(m, mk[padi(j0 + c)]);
         loc[c] = m;
     }
-    GH[t] = m;
-    __syncthreads();
-    for (int off = 1; off < tpl; off <<= 1) {
-        int val = GH[t];
-        if (t >= off) val = max(val, GH[t - off]);
-        __syncthreads();
-        GH[t] = val;
-        __syncthreads();
+    // inclusive scan over the lanes of this line: shuffles inside a wave
+    // (segments of tpl lanes when tpl < 64), wave totals through LDS
+    const int seg = tpl < kWave ? tpl : kWave;
+    int incl = m;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int o = __shfl_up(incl, off, seg);
+        if (off < seg && (t % seg) >= off) incl = max(incl, o);
     }
-    const int excl = t > 0 ? GH[t - 1] : -1;
+    int excl = __shfl_up(incl, 1, seg);
+    if (t % seg == 0) excl = -1;
+    if (tpl > kWave) {
+        const int w = tid / kWave;
+        if ((tid & (kWave - 1)) == kWave - 1) wave_tot[w] = incl;
+        __syncthreads();
+        const int wl0 = (l * tpl) / kWave;   // first wave of this line
+        for (int q = wl0; q < w; ++q) excl = max(excl, wave_tot[q]);
+    }
 
     // 5. evaluate at the selected vertex
-    T res[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int j = j0 + c;
-        res[c] = T(0);
         if (j < j1) {
             const int k = max(excl, loc[c]);
             const T d = T(j - k) * h;
-            res[c] = T(0.5) * d * d + v[k];
+            u[c] = T(0.5) * d * d + v[padi(k)];
         }
     }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        if (j0 + c < j1) vals[l * n + j0 + c] = res[c];
-    __syncthreads();
 
     if (inner == 1) {
-        for (int e = tid; e < tot; e += blockDim.x) {
-            const int ll = e / n, j = e - ll * n;
-            const long long L = L0 + ll;
-            if (L < nlines) out[L * n + j] = vals[e];
+        const bool vec = (n & 3) == 0 && (C & 3) == 0 && out_al;
+        if (L < nlines && j0 < j1) {
+            T *dst = out + L * n;
+#pragma unroll
+            for (int q = 0; q < C; q += 4) {
+                if (vec && j0 + q + 3 < n) {
+                    typename vec4<T>::type x;
+                    x.x = u[q]; x.y = u[q + 1]; x.z = u[q + 2]; x.w = u[q + 3];
+                    *reinterpret_cast<typename vec4<T>::type *>(dst + j0 + q) = x;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (q + e < C && j0 + q + e < n) dst[j0 + q + e] = u[q + e];
+                }
+            }
         }
     } else {
-        for (int e = tid; e < tot; e += blockDim.x) {
-            const int ll = e % lpb, j = e / lpb;
-            const long long L = L0 + ll;
-            if (L < nlines) out[line_base(L, n, inner) + (long long)j * inner] = vals[ll * n + j];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+        __syncthreads();
+        const bool vec = LPB == 4 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= nlines && out_al;
+        const long long base0 = line_base(L0, n, inner);
+        if (vec) {
+            for (int j = tid; j < n; j += nthr) {
+                const int pj = padi(j);
+                typename vec4<T>::type x;
+                x.x = vals[0 * NP + pj]; x.y = vals[1 * NP + pj]; x.z = vals[2 * NP + pj]; x.w = vals[3 * NP + pj];
+                *reinterpret_cast<typename vec4<T>::type *>(out + base0 + (long long)j * inner) = x;
+            }
+        } else {
+            for (int e = tid; e < LPB * n; e += nthr) {
+                const int ll = e % LPB, j = e / LPB;
+                const long long LL = L0 + ll;
+                if (LL < nlines) out[line_base(LL, n, inner) + (long long)j * inner] = vals[ll * NP + padi(j)];
+            }
         }
     }
 }
 
-constexpr int kCtChunk = 16;
+// Launch shape per line length: C points per lane, TPL = next power of two
+// >= n / C lanes per line, LPB lines per workgroup (4 for strided axes so
+// that each grid row is read as one 16-byte vector).
+struct CtShape {
+    int C, tpl, lpb, threads;
+};
 
-int ct_threads_per_line(int n) {
-    int need = (n + kCtChunk - 1) / kCtChunk;
-    int tpl = 1;
-    while (tpl < need) tpl <<= 1;
-    return tpl;
+static size_t ct_smem_for(int n, int tpl, int lpb, size_t esz)
+{
+    const size_t NP = (size_t)padded_len(n);
+    size_t b = (size_t)lpb * NP * esz + (size_t)lpb * 2 * NP * sizeof(short);
+    b = (b + 3) & ~(size_t)3;
+    return b + (size_t)lpb * 2 * tpl * sizeof(int);
 }
 
+constexpr size_t kCtLdsBudget = 150 * 1024;   // gfx950: 160 KB of LDS per CU
+
+static CtShape ct_shape(int n, bool strided, size_t esz)
+{
+    CtShape s;
+    s.C = n > 1024 ? 16 : 8;
+    const int need = (n + s.C - 1) / s.C;
+    s.tpl = 1;
+    while (s.tpl < need) s.tpl <<= 1;
+    if (strided) {
+        s.lpb = ct_smem_for(n, s.tpl, 4, esz) <= kCtLdsBudget ? 4 : 1;
+    } else {
+        s.lpb = s.tpl >= 256 ? 1 : 256 / s.tpl;
+        if (s.lpb > 64) s.lpb = 64;
+    }
+    s.threads = s.tpl * s.lpb;
+    if (s.threads < 64) {   // keep whole waves
+        s.lpb *= 64 / s.threads;
+        s.threads = 64;
+    }
+    return s;
+}
+
+int ct_threads_per_line(int n) { return ct_shape(n, false, 4).tpl; }
+
 template <typename T>
-size_t ct_smem_bytes(int n, int tpl, int lpb) {
-    size_t b = (size_t)lpb * n * sizeof(T);
-    b = (b + 3) & ~(size_t)3;
-    b += (size_t)lpb * n * 2 * sizeof(short);
-    b += (size_t)lpb * 2 * tpl * sizeof(int);
-    return b;
+size_t ct_smem_bytes(int n, int tpl, int lpb) { return ct_smem_for(n, tpl, lpb, sizeof(T)); }
+
+template <typename T, int C, int LPB>
+static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads,
+                                 T sgn, const int32_t *done, hipStream_t stream)
+{
+    const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
+    const long long blocks = (nlines + LPB - 1) / LPB;
+    const T h = T(1.0) / T(n);
+    if (smem > 64 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)ct_lines_kernel<T, C, LPB>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((ct_lines_kernel<T, C, LPB>), dim3((unsigned)blocks), dim3(threads), smem, stream, in,
+                       out, n, inner, nlines, tpl, sgn, h, done);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
                           const int32_t *done, hipStream_t stream)
 {
-    const int tpl = ct_threads_per_line(n);
-    if (tpl > 256) return hipErrorInvalidValue;
-    const int lpb = 256 / tpl;
-    const size_t smem = ct_smem_bytes<T>(n, tpl, lpb);
-    const long long blocks = (nlines + lpb - 1) / lpb;
-    const T h = T(1.0) / T(n);
-    hipLaunchKernelGGL((ct_lines_kernel<T, kCtChunk>), dim3((unsigned)blocks), dim3(256), smem, stream,
-                       in, out, n, inner, nlines, tpl, lpb, sgn, h, done);
-    return hipGetLastError();
+    const CtShape s = ct_shape(n, inner > 1, sizeof(T));
+    if (s.tpl > 256 || s.threads > 1024) return hipErrorInvalidValue;
+#define BFM_CT_CASE(CC, LL)                                                                               \
+    if (s.C == CC && s.lpb == LL)                                                                         \
+        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream);
+    BFM_CT_CASE(16, 1) BFM_CT_CASE(16, 4) BFM_CT_CASE(8, 1) BFM_CT_CASE(8, 2) BFM_CT_CASE(8, 4)
+    BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
+    BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64)
+#undef BFM_CT_CASE
+    return hipErrorInvalidValue;
 }
 
 // Full c-transform of a field: out = in^c, axis ndim-1 first (u = -in), then

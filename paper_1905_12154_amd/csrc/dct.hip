@@ -5,7 +5,9 @@
 // the Laplace inversion uses the FFT (Section 4.3).  On the cell-centred grid
 // the second-difference Neumann Laplacian is diagonalised by the DCT-II, with
 // eigenvalues lambda_k = sum_a 4 sin^2(pi k_a / (2 n_a)) n_a^2, so
-//     g = DCT3( DCT2(f) / lambda ),   zero mode dropped.
+//     g = DCT3( DCT2(f) / lambda ),   zero mode dropped,
+// and ||f - mean f||^2_{H^-1} = sum_k prod_a(w_a / n_a) X_k^2 / lambda_k with
+// w = 1 at k_a = 0 and 2 otherwise (Parseval for the unnormalised DCT-II).
 //
 // Transforms along one axis at a time (separable), unnormalised:
 //   DCT2:  X_k = sum_j x_j cos(pi k (2j+1) / (2n))
@@ -15,10 +17,29 @@
 // method); two real lines share one complex DFT (real and imaginary parts).
 // The DFT is a Stockham auto-sort FFT in LDS with radix 4, 2 and 3 stages
 // (n = 2^a 3^b), twiddles from a per-axis table.
+//
+// Passes (2D): forward along rows (input tgt - rho, rho cleared for the next
+// deposition) -> along columns forward, divide by lambda, inverse (one
+// kernel, G accumulated) -> inverse along rows writing p + sigma g.  3D adds a
+// forward and an inverse pass along the middle axis.  Contiguous axes move
+// 16-byte vectors per lane; strided axes process four adjacent lines per
+// workgroup so every grid row is one 16-byte vector.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace bfm {
+
+template <typename T> struct v4t;
+template <> struct v4t<float> { using type = float4; };
+template <> struct v4t<double> { using type = double4; };
+
+__device__ __forceinline__ int padc(int j) { return j + (j >> 4); }
+__host__ __device__ inline int padc_len(int n) { return n + (n >> 4) + 1; }
+
+__device__ __forceinline__ long long xcd_map(long long b, long long nb) {
+    const long long q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 template <typename T, int R>
 __device__ __forceinline__ void small_dft(cpx<T> *x) {
@@ -29,46 +50,48 @@ __device__ __forceinline__ void small_dft(cpx<T> *x) {
     } else if constexpr (R == 4) {
         const cpx<T> a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
         const cpx<T> c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
-        // forward transform: multiply d by -i
-        const cpx<T> dmi = {d.y, -d.x};
+        const cpx<T> dmi = {d.y, -d.x};   // -i d
         x[0] = cadd(a, c);
         x[1] = cadd(b, dmi);
         x[2] = csub(a, c);
         x[3] = csub(b, dmi);
-    } else {  // R == 3, omega = exp(-2 pi i / 3)
+    } else {   // R == 3, omega = exp(-2 pi i / 3)
         const T s3 = T(0.86602540378443864676);
         const cpx<T> a = x[0], b = x[1], c = x[2];
         const cpx<T> s = cadd(b, c), df = csub(b, c);
         const cpx<T> m = {a.x - T(0.5) * s.x, a.y - T(0.5) * s.y};
-        // -i * s3 * (b - c)
-        const cpx<T> r = {s3 * df.y, -s3 * df.x};
+        const cpx<T> r = {s3 * df.y, -s3 * df.x};   // -i s3 (b - c)
         x[0] = cadd(a, s);
         x[1] = cadd(m, r);
         x[2] = csub(m, r);
     }
 }
 
-// One Stockham stage: butterflies i = tid + q * blockDim (i < n/R), k = i mod p,
-// inputs buf[i + t n/R], twiddle exp(-2 pi i t k / (p R)), outputs at
-// (i - k) R + k + t p.  All reads complete before any write (barrier).
+// One Stockham stage on a padded LDS line (kept out of line: inlining all
+// stages of a transform into one body multiplies its register footprint):
+// butterflies i = lt + q * bd
+// (i < n/R), k = i mod p, inputs buf[i + t n/R], twiddle exp(-2 pi i t k/(p R)),
+// outputs at (i - k) R + k + t p.  All reads of the block complete before any
+// write (barrier); lines of one workgroup advance together.
 template <typename T, int VMAX, int R>
-__device__ __forceinline__ void fft_stage(cpx<T> *buf, int n, int p, const cpx<T> *__restrict__ tw) {
+__device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, int lt, int bd,
+                                          const cpx<T> *__restrict__ tw) {
     constexpr int NB = (VMAX + R - 1) / R;
     const int m = n / R;
     cpx<T> x[NB][R];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int i = threadIdx.x + q * blockDim.x;
+        const int i = lt + q * bd;
         if (i < m) {
 #pragma unroll
-            for (int t = 0; t < R; ++t) x[q][t] = buf[i + t * m];
+            for (int t = 0; t < R; ++t) x[q][t] = buf[padc(i + t * m)];
         }
     }
     __syncthreads();
     const int tstep = n / (p * R);
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int i = threadIdx.x + q * blockDim.x;
+        const int i = lt + q * bd;
         if (i < m) {
             const int k = i % p;
 #pragma unroll
@@ -76,27 +99,33 @@ __device__ __forceinline__ void fft_stage(cpx<T> *buf, int n, int p, const cpx<T
             small_dft<T, R>(x[q]);
             const int j = (i - k) * R + k;
 #pragma unroll
-            for (int t = 0; t < R; ++t) buf[j + t * p] = x[q][t];
+            for (int t = 0; t < R; ++t) buf[padc(j + t * p)] = x[q][t];
         }
     }
     __syncthreads();
 }
 
+// Stage counts are packed as radices = n4 | n2 << 8 | n3 << 16 (radix-4
+// stages first, then radix 2, then radix 3); one loop per radix keeps each
+// stage's register footprint separate.
 template <typename T, int VMAX>
-__device__ void fft_lds(cpx<T> *buf, int n, uint32_t radices, int nstages, const cpx<T> *__restrict__ tw) {
+__device__ void fft_lds(cpx<T> *buf, int n, uint32_t radices, int lt, int bd, const cpx<T> *__restrict__ tw) {
+    const int n4 = radices & 0xff, n2 = (radices >> 8) & 0xff, n3 = (radices >> 16) & 0xff;
     int p = 1;
-    for (int s = 0; s < nstages; ++s) {
-        const int R = (radices >> (2 * s)) & 3;   // 0 -> 4
-        if (R == 2) {
-            fft_stage<T, VMAX, 2>(buf, n, p, tw);
-            p *= 2;
-        } else if (R == 3) {
-            fft_stage<T, VMAX, 3>(buf, n, p, tw);
-            p *= 3;
-        } else {
-            fft_stage<T, VMAX, 4>(buf, n, p, tw);
-            p *= 4;
-        }
+#pragma unroll 1
+    for (int s = 0; s < n4; ++s) {
+        fft_stage<T, VMAX, 4>(buf, n, p, lt, bd, tw);
+        p *= 4;
+    }
+#pragma unroll 1
+    for (int s = 0; s < n2; ++s) {
+        fft_stage<T, VMAX, 2>(buf, n, p, lt, bd, tw);
+        p *= 2;
+    }
+#pragma unroll 1
+    for (int s = 0; s < n3; ++s) {
+        fft_stage<T, VMAX, 3>(buf, n, p, lt, bd, tw);
+        p *= 3;
     }
 }
 
@@ -104,209 +133,517 @@ __device__ __forceinline__ int makhoul_src(int j, int n) {
     return j < (n + 1) / 2 ? 2 * j : 2 * (n - 1 - j) + 1;
 }
 
-struct AxisArgs {
+struct DctArgs {
     int n, inner;
     long long nlines;
     uint32_t radices;
     int nstages;
+    // fused divide: other-axis eigenvalue tables and sizes (2D: A only)
+    int nA, nB;              // sizes of the other axes in line-index order (nB = 1 in 2D)
+    int innerB;              // line index = kA * nB + kB
 };
 
-// Forward DCT-II along one axis for two lines per block.  The input is
-// a - b when `b` is non-null (residual tgt - rho); when `zero_b` is set the
-// consumed entries of b are cleared afterwards (rho is re-zeroed for the
-// next deposition).
-template <typename T, int VMAX>
-__global__ void __launch_bounds__(256)
-dct2_lines_kernel(const T *a, T *b, T *out, AxisArgs ax, const cpx<T> *__restrict__ tw,
-                  const cpx<T> *__restrict__ qw, int zero_b, const int32_t *__restrict__ done)
-{
-    if (done != nullptr && *done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem);
-    const int n = ax.n, inner = ax.inner;
-    const long long La = 2LL * blockIdx.x, Lb = La + 1;
-    const bool hasb = Lb < ax.nlines;
-    const long long ba = line_base(La, n, inner), bb = hasb ? line_base(Lb, n, inner) : 0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const long long s = (long long)makhoul_src(j, n) * inner;
-        T xa = a[ba + s];
-        T xb = hasb ? a[bb + s] : T(0);
-        if (b != nullptr) {
-            xa -= b[ba + s];
-            if (hasb) xb -= b[bb + s];
-        }
-        buf[j] = {xa, xb};
-    }
-    __syncthreads();
-    if (zero_b && b != nullptr) {
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            b[ba + (long long)j * inner] = T(0);
-            if (hasb) b[bb + (long long)j * inner] = T(0);
-        }
-    }
-    fft_lds<T, VMAX>(buf, n, ax.radices, ax.nstages, tw);
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const cpx<T> z = buf[k];
-        const cpx<T> zc = conj_(buf[k == 0 ? 0 : n - k]);
-        const cpx<T> va = {T(0.5) * (z.x + zc.x), T(0.5) * (z.y + zc.y)};
-        const cpx<T> dd = csub(z, zc);
-        const cpx<T> vb = {T(0.5) * dd.y, T(-0.5) * dd.x};
-        const cpx<T> w = qw[k];   // exp(-i pi k / (2n))
-        out[ba + (long long)k * inner] = w.x * va.x - w.y * va.y;
-        if (hasb) out[bb + (long long)k * inner] = w.x * vb.x - w.y * vb.y;
-    }
-}
+enum DctMode { DM_FWD = 0, DM_INV = 1, DM_FUSED = 2 };
 
-// Inverse (DCT-III / n) along one axis for two lines per block.  With
-// `base` non-null the result is written as out = base + (*scale) * x (the
-// gradient step p + sigma g, sigma read from device memory).
-template <typename T, int VMAX>
-__global__ void __launch_bounds__(256)
-dct3_lines_kernel(const T *in, T *out, const T *base, const double *scale, AxisArgs ax,
-                  const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw,
-                  const int32_t *__restrict__ done)
-{
-    if (done != nullptr && *done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem);
-    const int n = ax.n, inner = ax.inner;
-    const long long La = 2LL * blockIdx.x, Lb = La + 1;
-    const bool hasb = Lb < ax.nlines;
-    const long long ba = line_base(La, n, inner), bb = hasb ? line_base(Lb, n, inner) : 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const long long s = (long long)k * inner;
-        buf[k] = {in[ba + s], hasb ? in[bb + s] : T(0)};
-    }
-    __syncthreads();
-    // W_k = X_k - i X_{n-k} (X_n = 0), V_k = exp(+i pi k/(2n)) W_k, Z = V_a + i V_b;
-    // the inverse DFT is conj(DFT(conj(Z))) / n, so conj(Z) is staged.
-    constexpr int KMAX = VMAX;
-    cpx<T> zr[KMAX];
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-        const int k = threadIdx.x + q * blockDim.x;
-        if (k < n) {
-            const cpx<T> xk = buf[k];
-            const cpx<T> xr = k == 0 ? cpx<T>{T(0), T(0)} : buf[n - k];
-            const cpx<T> w = conj_(qw[k]);
-            const cpx<T> wa = {xk.x, -xr.x}, wb = {xk.y, -xr.y};
-            const cpx<T> va = cmul(w, wa), vb = cmul(w, wb);
-            const cpx<T> z = {va.x - vb.y, va.y + vb.x};
-            zr[q] = conj_(z);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-        const int k = threadIdx.x + q * blockDim.x;
-        if (k < n) buf[k] = zr[q];
-    }
-    __syncthreads();
-    fft_lds<T, VMAX>(buf, n, ax.radices, ax.nstages, tw);
-    const T inv_n = T(1) / T(n);
-    const T sc = scale != nullptr ? T(*scale) : T(1);
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const cpx<T> z = buf[j];   // conj of the inverse transform times n
-        const long long s = (long long)makhoul_src(j, n) * inner;
-        const T xa = z.x * inv_n, xb = -z.y * inv_n;
-        if (base != nullptr) {
-            out[ba + s] = base[ba + s] + sc * xa;
-            if (hasb) out[bb + s] = base[bb + s] + sc * xb;
-        } else {
-            out[ba + s] = xa;
-            if (hasb) out[bb + s] = xb;
-        }
-    }
-}
-
-// X_k /= lambda_k (zero mode set to 0) and the partial of
-// sum_k prod_a(w_a / n_a) X_k^2 / lambda_k, w = 1 at k_a = 0 and 2 otherwise.
+// After a forward FFT of z = v_a + i v_b in buf, the DCT-II coefficients of
+// lines a and b at index k.
 template <typename T>
-__global__ void __launch_bounds__(kRedBlock)
-spectral_divide_kernel(T *X, Grid g, const T *__restrict__ lam0, const T *__restrict__ lam1,
-                       const T *__restrict__ lam2, double *__restrict__ part, const int32_t *__restrict__ done)
-{
-    if (done != nullptr && *done) return;
-    __shared__ double sh[kRedBlock / kWave];
-    double acc = 0.0;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
-         idx += (long long)gridDim.x * blockDim.x) {
-        long long r = idx;
-        int k[3] = {0, 0, 0};
-        for (int a = g.ndim - 1; a >= 0; --a) {
-            k[a] = (int)(r % g.n[a]);
-            r /= g.n[a];
-        }
-        const T lam = lam0[k[0]] + lam1[k[1]] + (g.ndim == 3 ? lam2[k[2]] : T(0));
-        const T x = X[idx];
-        if (idx == 0) {
-            X[idx] = T(0);
-        } else {
-            const T y = x / lam;
-            X[idx] = y;
-            double w = 1.0;
-            for (int a = 0; a < g.ndim; ++a) w *= (k[a] == 0 ? 1.0 : 2.0) / g.n[a];
-            acc += w * (double)x * (double)y;
-        }
-    }
-    const double s = block_reduce<R_SUM>(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+__device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, const cpx<T> *__restrict__ qw, T &Xa,
+                                          T &Xb) {
+    const cpx<T> z = buf[padc(k)];
+    const cpx<T> zc = conj_(buf[padc(k == 0 ? 0 : n - k)]);
+    const cpx<T> va = {T(0.5) * (z.x + zc.x), T(0.5) * (z.y + zc.y)};
+    const cpx<T> dd = csub(z, zc);
+    const cpx<T> vb = {T(0.5) * dd.y, T(-0.5) * dd.x};
+    const cpx<T> w = qw[k];   // exp(-i pi k / (2n))
+    Xa = w.x * va.x - w.y * va.y;
+    Xb = w.x * vb.x - w.y * vb.y;
 }
 
-template <typename T> constexpr int dct_vmax() { return 16; }
+// Before an inverse: from coefficients (X_a[k], X_b[k]) staged in buf, the
+// conjugate of Z_k = e^{i pi k/(2n)} ((X_a[k] - i X_a[n-k]) + i (X_b[k] - i X_b[n-k])).
+template <typename T>
+__device__ __forceinline__ cpx<T> dct3_pre(const cpx<T> *buf, int n, int k, const cpx<T> *__restrict__ qw) {
+    const cpx<T> xk = buf[padc(k)];
+    const cpx<T> xr = k == 0 ? cpx<T>{T(0), T(0)} : buf[padc(n - k)];
+    const cpx<T> w = conj_(qw[k]);
+    const cpx<T> wa = {xk.x, -xr.x}, wb = {xk.y, -xr.y};
+    const cpx<T> va = cmul(w, wa), vb = cmul(w, wb);
+    return conj_(cpx<T>{va.x - vb.y, va.y + vb.x});
+}
+
+// Sum over the block (blockDim.x a multiple of 64, at most 512); valid in thread 0.
+__device__ __forceinline__ double block_sum_any(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+// Line transforms along one axis.  NPAIR pairs of lines (2 NPAIR lines) per
+// workgroup, bd lanes per pair.  CONTIG: lines are contiguous (axis ndim-1,
+// NPAIR = 1); otherwise four adjacent lines are read/written as 16-byte vectors.
+template <typename T, int VMAX, int NPAIR, int MODE, bool CONTIG>
+__global__ void __launch_bounds__(512)
+dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, DctArgs ax, int zero_b,
+                 const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw, const T *__restrict__ lam0,
+                 const T *__restrict__ lamA, const T *__restrict__ lamB, double *__restrict__ gpart,
+                 const int32_t *__restrict__ done)
+{
+    if (done != nullptr && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[8];
+    const int n = ax.n, inner = ax.inner;
+    const int NPC = padc_len(n);
+    const int bd = blockDim.x / NPAIR;
+    const int pr = threadIdx.x / bd, lt = threadIdx.x - pr * bd;
+    cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem) + (size_t)pr * NPC;
+    const long long blk = xcd_map(blockIdx.x, gridDim.x);
+    const long long L0 = blk * (2 * NPAIR);          // first line of the workgroup
+    const long long La = L0 + 2 * pr, Lb = La + 1;   // this pair
+    const bool hasa = La < ax.nlines, hasb = Lb < ax.nlines;
+    const bool al16 = (((uintptr_t)a | (uintptr_t)out | (uintptr_t)(b != nullptr ? b : a) |
+                        (uintptr_t)(base != nullptr ? base : a)) & 15) == 0;
+
+    // ---------------------------------------------------------------- load
+    if (MODE == DM_INV) {
+        // coefficients (X_a[k], X_b[k]) into buf
+        if (CONTIG) {
+            const long long ba = La * n, bbb = Lb * n;
+            const bool vec = (n & 3) == 0 && al16;
+            for (int k4 = lt * 4; k4 < n; k4 += bd * 4) {
+                if (vec) {
+                    typename v4t<T>::type xa = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + k4);
+                    typename v4t<T>::type xb;
+                    if (hasb) xb = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + k4);
+                    else xb.x = xb.y = xb.z = xb.w = T(0);
+                    buf[padc(k4)] = {xa.x, xb.x};
+                    buf[padc(k4 + 1)] = {xa.y, xb.y};
+                    buf[padc(k4 + 2)] = {xa.z, xb.z};
+                    buf[padc(k4 + 3)] = {xa.w, xb.w};
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (k4 + e < n) buf[padc(k4 + e)] = {hasa ? a[ba + k4 + e] : T(0), hasb ? a[bbb + k4 + e] : T(0)};
+                }
+            }
+        } else {
+            const bool vec = NPAIR == 2 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= ax.nlines && al16;
+            const long long b0 = line_base(L0, n, inner);
+            cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
+            cpx<T> *buf1 = buf0 + NPC;
+            if (vec) {
+                for (int k = threadIdx.x; k < n; k += blockDim.x) {
+                    const typename v4t<T>::type x =
+                        *reinterpret_cast<const typename v4t<T>::type *>(a + b0 + (long long)k * inner);
+                    buf0[padc(k)] = {x.x, x.y};
+                    buf1[padc(k)] = {x.z, x.w};
+                }
+            } else {
+                for (int k = lt; k < n; k += bd)
+                    buf[padc(k)] = {hasa ? a[line_base(La, n, inner) + (long long)k * inner] : T(0),
+                                    hasb ? a[line_base(Lb, n, inner) + (long long)k * inner] : T(0)};
+            }
+        }
+        __syncthreads();
+        cpx<T> zr[VMAX];
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) zr[q] = dct3_pre(buf, n, k, qw);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) buf[padc(k)] = zr[q];
+        }
+    } else {
+        // real samples, reordered: v_j = x_{2j}, v_{n-1-j} = x_{2j+1}
+        if (CONTIG) {
+            const long long ba = La * n, bbb = Lb * n;
+            const bool vec = (n & 3) == 0 && al16;
+            for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
+                T xa[4], xb[4];
+                if (vec) {
+                    typename v4t<T>::type va4 = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + j4);
+                    typename v4t<T>::type vb4;
+                    if (hasb) vb4 = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + j4);
+                    else vb4.x = vb4.y = vb4.z = vb4.w = T(0);
+                    if (b != nullptr) {
+                        const typename v4t<T>::type ra = *reinterpret_cast<const typename v4t<T>::type *>(b + ba + j4);
+                        va4.x -= ra.x; va4.y -= ra.y; va4.z -= ra.z; va4.w -= ra.w;
+                        if (hasb) {
+                            const typename v4t<T>::type rb =
+                                *reinterpret_cast<const typename v4t<T>::type *>(b + bbb + j4);
+                            vb4.x -= rb.x; vb4.y -= rb.y; vb4.z -= rb.z; vb4.w -= rb.w;
+                        }
+                        if (zero_b) {
+                            typename v4t<T>::type z;
+                            z.x = z.y = z.z = z.w = T(0);
+                            *reinterpret_cast<typename v4t<T>::type *>(b + ba + j4) = z;
+                            if (hasb) *reinterpret_cast<typename v4t<T>::type *>(b + bbb + j4) = z;
+                        }
+                    }
+                    xa[0] = va4.x; xa[1] = va4.y; xa[2] = va4.z; xa[3] = va4.w;
+                    xb[0] = vb4.x; xb[1] = vb4.y; xb[2] = vb4.z; xb[3] = vb4.w;
+                    // x_{j4}, x_{j4+2} are even samples, x_{j4+1}, x_{j4+3} odd
+                    buf[padc(j4 / 2)] = {xa[0], xb[0]};
+                    buf[padc(j4 / 2 + 1)] = {xa[2], xb[2]};
+                    buf[padc(n - 1 - j4 / 2)] = {xa[1], xb[1]};
+                    buf[padc(n - 2 - j4 / 2)] = {xa[3], xb[3]};
+                } else {
+                    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (j4 + e >= n) break;
+                        const int jj = j4 + e;
+                        T ya = hasa ? a[ba + jj] : T(0), yb = hasb ? a[bbb + jj] : T(0);
+                        if (b != nullptr) {
+                            if (hasa) ya -= b[ba + jj];
+                            if (hasb) yb -= b[bbb + jj];
+                            if (zero_b) {
+                                if (hasa) b[ba + jj] = T(0);
+                                if (hasb) b[bbb + jj] = T(0);
+                            }
+                        }
+                        const int pos = (jj & 1) ? n - 1 - (jj >> 1) : (jj >> 1);
+                        buf[padc(pos)] = {ya, yb};
+                    }
+                }
+            }
+        } else {
+            const bool vec = NPAIR == 2 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= ax.nlines && al16;
+            const long long b0 = line_base(L0, n, inner);
+            cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
+            cpx<T> *buf1 = buf0 + NPC;
+            if (vec) {
+                for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                    const typename v4t<T>::type x = *reinterpret_cast<const typename v4t<T>::type *>(
+                        a + b0 + (long long)makhoul_src(j, n) * inner);
+                    buf0[padc(j)] = {x.x, x.y};
+                    buf1[padc(j)] = {x.z, x.w};
+                }
+            } else {
+                for (int j = lt; j < n; j += bd) {
+                    const long long s = (long long)makhoul_src(j, n) * inner;
+                    buf[padc(j)] = {hasa ? a[line_base(La, n, inner) + s] : T(0),
+                                    hasb ? a[line_base(Lb, n, inner) + s] : T(0)};
+                }
+            }
+        }
+    }
+    __syncthreads();
+    fft_lds<T, VMAX>(buf, n, ax.radices, lt, bd, tw);
+
+    double gacc = 0.0;
+    if (MODE == DM_FUSED) {
+        // coefficients along this axis, divided by lambda; restage for the inverse
+        T ya[VMAX], yb[VMAX];
+        // eigenvalue and weight of the other axes for lines a and b
+        T lra = T(0), lrb = T(0);
+        double wra = 1.0, wrb = 1.0;
+        {
+            const long long Ls[2] = {La, Lb};
+            for (int s = 0; s < 2; ++s) {
+                const long long Lx = Ls[s] < ax.nlines ? Ls[s] : 0;
+                const int kA = (int)(Lx / ax.nB), kB = (int)(Lx % ax.nB);
+                const T lr = lamA[kA] + (ax.nB > 1 ? lamB[kB] : T(0));
+                const double wr = ((kA == 0) ? 1.0 : 2.0) / ax.nA * (ax.nB > 1 ? ((kB == 0) ? 1.0 : 2.0) / ax.nB : 1.0);
+                if (s == 0) { lra = lr; wra = wr; } else { lrb = lr; wrb = wr; }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) {
+                T Xa, Xb;
+                dct2_post(buf, n, k, qw, Xa, Xb);
+                const T l0 = lam0[k];
+                const T la = l0 + lra, lb = l0 + lrb;
+                const double wk = (k == 0 ? 1.0 : 2.0) / n;
+                ya[q] = la > T(0) ? Xa / la : T(0);
+                yb[q] = lb > T(0) ? Xb / lb : T(0);
+                if (hasa) gacc += wk * wra * (double)Xa * (double)ya[q];
+                if (hasb) gacc += wk * wrb * (double)Xb * (double)yb[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) buf[padc(k)] = {ya[q], yb[q]};
+        }
+        __syncthreads();
+        cpx<T> zr[VMAX];
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) zr[q] = dct3_pre(buf, n, k, qw);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int k = lt + q * bd;
+            if (k < n) buf[padc(k)] = zr[q];
+        }
+        __syncthreads();
+        fft_lds<T, VMAX>(buf, n, ax.radices, lt, bd, tw);
+    }
+
+    // --------------------------------------------------------------- store
+    if (MODE == DM_FWD) {
+        if (CONTIG) {
+            const long long ba = La * n, bbb = Lb * n;
+            const bool vec = (n & 3) == 0 && al16;
+            for (int k4 = lt * 4; k4 < n; k4 += bd * 4) {
+                T Xa[4], Xb[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    Xa[e] = Xb[e] = T(0);
+                    if (k4 + e < n) dct2_post(buf, n, k4 + e, qw, Xa[e], Xb[e]);
+                }
+                if (vec) {
+                    typename v4t<T>::type oa, ob;
+                    oa.x = Xa[0]; oa.y = Xa[1]; oa.z = Xa[2]; oa.w = Xa[3];
+                    ob.x = Xb[0]; ob.y = Xb[1]; ob.z = Xb[2]; ob.w = Xb[3];
+                    if (hasa) *reinterpret_cast<typename v4t<T>::type *>(out + ba + k4) = oa;
+                    if (hasb) *reinterpret_cast<typename v4t<T>::type *>(out + bbb + k4) = ob;
+                } else {
+                    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (k4 + e >= n) break;
+                        if (hasa) out[ba + k4 + e] = Xa[e];
+                        if (hasb) out[bbb + k4 + e] = Xb[e];
+                    }
+                }
+            }
+        } else {
+            const bool vec = NPAIR == 2 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= ax.nlines && al16;
+            const long long b0 = line_base(L0, n, inner);
+            if (vec) {
+                // thread owns (pair, k): gather both pairs through registers
+                cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
+                cpx<T> *buf1 = buf0 + NPC;
+                for (int k = threadIdx.x; k < n; k += blockDim.x) {
+                    T a0, b0v, a1, b1v;
+                    dct2_post(buf0, n, k, qw, a0, b0v);
+                    dct2_post(buf1, n, k, qw, a1, b1v);
+                    typename v4t<T>::type o;
+                    o.x = a0; o.y = b0v; o.z = a1; o.w = b1v;
+                    *reinterpret_cast<typename v4t<T>::type *>(out + b0 + (long long)k * inner) = o;
+                }
+            } else {
+                for (int k = lt; k < n; k += bd) {
+                    T Xa, Xb;
+                    dct2_post(buf, n, k, qw, Xa, Xb);
+                    if (hasa) out[line_base(La, n, inner) + (long long)k * inner] = Xa;
+                    if (hasb) out[line_base(Lb, n, inner) + (long long)k * inner] = Xb;
+                }
+            }
+        }
+    } else {
+        // inverse result: buf_j = n conj(z_j); x[src(j)] = Re z_j (line a), Im z_j (line b)
+        const T inv_n = T(1) / T(n);
+        const T sc = scale != nullptr ? T(*scale) : T(1);
+        if (CONTIG) {
+            const long long ba = La * n, bbb = Lb * n;
+            const bool vec = (n & 3) == 0 && al16;
+            for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
+                T xa[4], xb[4];
+                #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (j4 + e >= n) break;
+                    const int jj = j4 + e;
+                    const int pos = (jj & 1) ? n - 1 - (jj >> 1) : (jj >> 1);
+                    const cpx<T> z = buf[padc(pos)];
+                    xa[e] = z.x * inv_n;
+                    xb[e] = -z.y * inv_n;
+                }
+                if (vec) {
+                    typename v4t<T>::type oa, ob;
+                    oa.x = xa[0]; oa.y = xa[1]; oa.z = xa[2]; oa.w = xa[3];
+                    ob.x = xb[0]; ob.y = xb[1]; ob.z = xb[2]; ob.w = xb[3];
+                    if (base != nullptr) {
+                        const typename v4t<T>::type pa = *reinterpret_cast<const typename v4t<T>::type *>(base + ba + j4);
+                        oa.x = pa.x + sc * oa.x; oa.y = pa.y + sc * oa.y; oa.z = pa.z + sc * oa.z; oa.w = pa.w + sc * oa.w;
+                        if (hasb) {
+                            const typename v4t<T>::type pb =
+                                *reinterpret_cast<const typename v4t<T>::type *>(base + bbb + j4);
+                            ob.x = pb.x + sc * ob.x; ob.y = pb.y + sc * ob.y; ob.z = pb.z + sc * ob.z; ob.w = pb.w + sc * ob.w;
+                        }
+                    }
+                    if (hasa) *reinterpret_cast<typename v4t<T>::type *>(out + ba + j4) = oa;
+                    if (hasb) *reinterpret_cast<typename v4t<T>::type *>(out + bbb + j4) = ob;
+                } else {
+                    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (j4 + e >= n) break;
+                        const long long ia = ba + j4 + e, ib = bbb + j4 + e;
+                        if (hasa) out[ia] = base != nullptr ? base[ia] + sc * xa[e] : xa[e];
+                        if (hasb) out[ib] = base != nullptr ? base[ib] + sc * xb[e] : xb[e];
+                    }
+                }
+            }
+        } else {
+            const bool vec = NPAIR == 2 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= ax.nlines && al16;
+            const long long b0 = line_base(L0, n, inner);
+            if (vec) {
+                cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
+                cpx<T> *buf1 = buf0 + NPC;
+                for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                    const cpx<T> z0 = buf0[padc(j)], z1 = buf1[padc(j)];
+                    typename v4t<T>::type o;
+                    o.x = z0.x * inv_n; o.y = -z0.y * inv_n; o.z = z1.x * inv_n; o.w = -z1.y * inv_n;
+                    const long long addr = b0 + (long long)makhoul_src(j, n) * inner;
+                    if (base != nullptr) {
+                        const typename v4t<T>::type p = *reinterpret_cast<const typename v4t<T>::type *>(base + addr);
+                        o.x = p.x + sc * o.x; o.y = p.y + sc * o.y; o.z = p.z + sc * o.z; o.w = p.w + sc * o.w;
+                    }
+                    *reinterpret_cast<typename v4t<T>::type *>(out + addr) = o;
+                }
+            } else {
+                for (int j = lt; j < n; j += bd) {
+                    const cpx<T> z = buf[padc(j)];
+                    const long long s = (long long)makhoul_src(j, n) * inner;
+                    const T xa = z.x * inv_n, xb = -z.y * inv_n;
+                    if (hasa) {
+                        const long long ia = line_base(La, n, inner) + s;
+                        out[ia] = base != nullptr ? base[ia] + sc * xa : xa;
+                    }
+                    if (hasb) {
+                        const long long ib = line_base(Lb, n, inner) + s;
+                        out[ib] = base != nullptr ? base[ib] + sc * xb : xb;
+                    }
+                }
+            }
+        }
+    }
+    if (MODE == DM_FUSED) {
+        const double gs = block_sum_any(gacc, red);
+        if (threadIdx.x == 0) gpart[blockIdx.x] = gs;
+    }
+}
 
 static int dct_block(int n) {
     int bd = 64;
-    while (bd * 16 < n) bd <<= 1;   // n / blockDim <= 16 complex values per lane
+    while (bd * 16 < n) bd <<= 1;   // n / bd <= 16 complex values per lane
     return bd;
 }
 
-template <typename T>
-hipError_t launch_dct2_axis(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b,
-                            const void *tw, const void *qw, const int32_t *done, hipStream_t stream)
+template <typename T, int NPAIR, int MODE, bool CONTIG>
+static hipError_t launch_dct_impl(const T *a, T *b, T *out, const T *base, const double *scale, const DctArgs &ax,
+                                  int zero_b, const void *tw, const void *qw, const T *lam0, const T *lamA,
+                                  const T *lamB, double *gpart, const int32_t *done, hipStream_t stream)
 {
-    AxisArgs ax{ap.n, ap.inner, N / ap.n, ap.radices, ap.nstages};
-    const long long blocks = (ax.nlines + 1) / 2;
-    const int bd = dct_block(ap.n);
-    if (bd > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((dct2_lines_kernel<T, 16>), dim3((unsigned)blocks), dim3(bd),
-                       (size_t)ap.n * sizeof(cpx<T>), stream, a, b, out, ax,
-                       (const cpx<T> *)tw, (const cpx<T> *)qw, zero_b, done);
+    const int bd = dct_block(ax.n);
+    if (bd * NPAIR > 512) return hipErrorInvalidValue;
+    const size_t smem = (size_t)NPAIR * padc_len(ax.n) * sizeof(cpx<T>);
+    const long long blocks = (ax.nlines + 2 * NPAIR - 1) / (2 * NPAIR);
+    if (smem > 64 * 1024) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>), dim3((unsigned)blocks), dim3(bd * NPAIR),
+                       smem, stream, a, b, out, base, scale, ax, zero_b, (const cpx<T> *)tw, (const cpx<T> *)qw,
+                       lam0, lamA, lamB, gpart, done);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_dct3_axis(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap,
-                            long long N, const void *tw, const void *qw, const int32_t *done,
-                            hipStream_t stream)
-{
-    AxisArgs ax{ap.n, ap.inner, N / ap.n, ap.radices, ap.nstages};
-    const long long blocks = (ax.nlines + 1) / 2;
-    const int bd = dct_block(ap.n);
-    if (bd > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((dct3_lines_kernel<T, 16>), dim3((unsigned)blocks), dim3(bd),
-                       (size_t)ap.n * sizeof(cpx<T>), stream, in, out, base, scale, ax,
-                       (const cpx<T> *)tw, (const cpx<T> *)qw, done);
-    return hipGetLastError();
+static DctArgs make_args(const AxisPlan &ap, long long N) {
+    DctArgs ax{};
+    ax.n = ap.n;
+    ax.inner = ap.inner;
+    ax.nlines = N / ap.n;
+    ax.radices = ap.radices;
+    ax.nstages = ap.nstages;
+    ax.nA = 1;
+    ax.nB = 1;
+    ax.innerB = 1;
+    return ax;
+}
+
+// Strided axes use two pairs (four lines) per workgroup when LDS allows.
+template <typename T> static bool dct_two_pairs(int n) {
+    return (size_t)2 * padc_len(n) * sizeof(cpx<T>) <= 150 * 1024;
 }
 
 template <typename T>
-hipError_t launch_spectral_divide(T *X, const Grid &g, const T *lam0, const T *lam1, const T *lam2,
-                                  double *part, int nblocks, const int32_t *done, hipStream_t stream)
+hipError_t launch_dct_fwd(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b, const void *tw,
+                          const void *qw, const int32_t *done, hipStream_t stream)
 {
-    hipLaunchKernelGGL((spectral_divide_kernel<T>), dim3(nblocks), dim3(kRedBlock), 0, stream, X, g,
-                       lam0, lam1, lam2, part, done);
-    return hipGetLastError();
+    const DctArgs ax = make_args(ap, N);
+    if (ap.inner == 1)
+        return launch_dct_impl<T, 1, DM_FWD, true>(a, b, out, nullptr, nullptr, ax, zero_b, tw, qw, nullptr, nullptr,
+                                                   nullptr, nullptr, done, stream);
+    if (b != nullptr) return hipErrorInvalidValue;
+    if (dct_two_pairs<T>(ap.n))
+        return launch_dct_impl<T, 2, DM_FWD, false>(a, nullptr, out, nullptr, nullptr, ax, 0, tw, qw, nullptr,
+                                                    nullptr, nullptr, nullptr, done, stream);
+    return launch_dct_impl<T, 1, DM_FWD, false>(a, nullptr, out, nullptr, nullptr, ax, 0, tw, qw, nullptr, nullptr,
+                                                nullptr, nullptr, done, stream);
 }
 
-#define BFM_INST_DCT(T)                                                                                     \
-    template hipError_t launch_dct2_axis<T>(const T *, T *, T *, const AxisPlan &, long long, int,          \
-                                            const void *, const void *, const int32_t *, hipStream_t);      \
-    template hipError_t launch_dct3_axis<T>(const T *, T *, const T *, const double *, const AxisPlan &,    \
-                                            long long, const void *, const void *, const int32_t *,         \
-                                            hipStream_t);                                                   \
-    template hipError_t launch_spectral_divide<T>(T *, const Grid &, const T *, const T *, const T *,       \
-                                                  double *, int, const int32_t *, hipStream_t);
+template <typename T>
+hipError_t launch_dct_inv(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap, long long N,
+                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream)
+{
+    const DctArgs ax = make_args(ap, N);
+    if (ap.inner == 1)
+        return launch_dct_impl<T, 1, DM_INV, true>(in, nullptr, out, base, scale, ax, 0, tw, qw, nullptr, nullptr,
+                                                   nullptr, nullptr, done, stream);
+    if (dct_two_pairs<T>(ap.n))
+        return launch_dct_impl<T, 2, DM_INV, false>(in, nullptr, out, base, scale, ax, 0, tw, qw, nullptr, nullptr,
+                                                    nullptr, nullptr, done, stream);
+    return launch_dct_impl<T, 1, DM_INV, false>(in, nullptr, out, base, scale, ax, 0, tw, qw, nullptr, nullptr,
+                                                nullptr, nullptr, done, stream);
+}
+
+// Along axis 0: forward, divide by lambda = lam0[k0] + lamA[kA] (+ lamB[kB]),
+// inverse; per-workgroup partials of G into gpart (one per workgroup).
+template <typename T>
+hipError_t launch_dct_fused(T *X, const AxisPlan &ap0, long long N, int nA, int nB, const void *tw, const void *qw,
+                            const T *lam0, const T *lamA, const T *lamB, double *gpart, int *nparts,
+                            const int32_t *done, hipStream_t stream)
+{
+    DctArgs ax = make_args(ap0, N);
+    ax.nA = nA;
+    ax.nB = nB;
+    const bool two = dct_two_pairs<T>(ap0.n) && ap0.inner > 1;
+    const int per = two ? 4 : 2;
+    *nparts = (int)((ax.nlines + per - 1) / per);
+    if (ap0.inner == 1) return hipErrorInvalidValue;
+    if (two)
+        return launch_dct_impl<T, 2, DM_FUSED, false>(X, nullptr, X, nullptr, nullptr, ax, 0, tw, qw, lam0, lamA,
+                                                      lamB, gpart, done, stream);
+    return launch_dct_impl<T, 1, DM_FUSED, false>(X, nullptr, X, nullptr, nullptr, ax, 0, tw, qw, lam0, lamA, lamB,
+                                                  gpart, done, stream);
+}
+
+long long dct_fused_parts(int n0, long long N, size_t esz)
+{
+    const bool two = (size_t)2 * padc_len(n0) * 2 * esz <= 150 * 1024;
+    const long long nl = N / n0;
+    return two ? (nl + 3) / 4 : (nl + 1) / 2;
+}
+
+#define BFM_INST_DCT(T)                                                                                       \
+    template hipError_t launch_dct_fwd<T>(const T *, T *, T *, const AxisPlan &, long long, int, const void *, \
+                                          const void *, const int32_t *, hipStream_t);                         \
+    template hipError_t launch_dct_inv<T>(const T *, T *, const T *, const double *, const AxisPlan &,        \
+                                          long long, const void *, const void *, const int32_t *,             \
+                                          hipStream_t);                                                       \
+    template hipError_t launch_dct_fused<T>(T *, const AxisPlan &, long long, int, int, const void *,         \
+                                            const void *, const T *, const T *, const T *, double *, int *,    \
+                                            const int32_t *, hipStream_t);
 BFM_INST_DCT(float)
 BFM_INST_DCT(double)
 

@@ -5,8 +5,8 @@
 
 namespace bfm {
 
-// Per-axis spectral plan: FFT radix sequence (2 bits per stage: 0 -> 4,
-// 2 -> 2, 3 -> 3) and the stride of the axis.
+// Per-axis spectral plan: FFT stage counts (n = 4^n4 2^n2 3^n3 packed as
+// n4 | n2 << 8 | n3 << 16) and the stride of the axis.
 struct AxisPlan {
     int n;
     int inner;
@@ -25,15 +25,16 @@ template <typename T> size_t ct_smem_bytes(int n, int tpl, int lpb);
 
 // DCT Poisson (dct.hip)
 template <typename T>
-hipError_t launch_dct2_axis(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b,
-                            const void *tw, const void *qw, const int32_t *done, hipStream_t stream);
+hipError_t launch_dct_fwd(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b, const void *tw,
+                          const void *qw, const int32_t *done, hipStream_t stream);
 template <typename T>
-hipError_t launch_dct3_axis(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap,
-                            long long N, const void *tw, const void *qw, const int32_t *done,
-                            hipStream_t stream);
+hipError_t launch_dct_inv(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap, long long N,
+                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream);
 template <typename T>
-hipError_t launch_spectral_divide(T *X, const Grid &g, const T *lam0, const T *lam1, const T *lam2,
-                                  double *part, int nblocks, const int32_t *done, hipStream_t stream);
+hipError_t launch_dct_fused(T *X, const AxisPlan &ap0, long long N, int nA, int nB, const void *tw, const void *qw,
+                            const T *lam0, const T *lamA, const T *lamB, double *gpart, int *nparts,
+                            const int32_t *done, hipStream_t stream);
+long long dct_fused_parts(int n0, long long N, size_t esz);
 
 // map, pushforward, reductions, controller (pushforward.hip, reduce.hip)
 template <typename T>
@@ -66,7 +67,7 @@ struct CtrlParams {
     double tol, sigma0, sigma_min, beta1, beta2, alpha1, alpha2, vol, inv_N;
 };
 
-hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, int mode, CtrlParams prm,
-                       TraceRec *trace, hipStream_t stream);
+hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, const double *gpart, int ngpart,
+                       int mode, CtrlParams prm, TraceRec *trace, hipStream_t stream);
 
 }  // namespace bfm

@@ -159,7 +159,8 @@ __device__ double step_rule(double sigma, double increase, double G, const CtrlP
 }
 
 __global__ void __launch_bounds__(kRedBlock)
-ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, int mode, CtrlParams prm, TraceRec *trace)
+ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const double *__restrict__ gpart, int ng,
+            int mode, CtrlParams prm, TraceRec *trace)
 {
     __shared__ double sh[kRedBlock / kWave];
     if (mode == CTRL_INIT) {
@@ -203,7 +204,9 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, int mode,
         const double a = slot_reduce_sum(partials, S_P_TGT, nb, sh);
         const double b = slot_reduce_sum(partials, S_PC_SRC, nb, sh);
         const double P = slot_reduce_sum(partials, S_PRIMAL, nb, sh);
-        const double G = slot_reduce_sum(partials, S_G, nb, sh);
+        double gv = 0.0;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) gv += gpart[i];
+        const double G = block_reduce<R_SUM>(gv, sh);
         if (threadIdx.x == 0) {
             st->J_old = prm.vol * (a + b);
             st->P = prm.vol * P;
@@ -258,10 +261,11 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, int mode,
     }
 }
 
-hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, int mode, CtrlParams prm,
-                       TraceRec *trace, hipStream_t stream)
+hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, const double *gpart, int ngpart,
+                       int mode, CtrlParams prm, TraceRec *trace, hipStream_t stream)
 {
-    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(kRedBlock), 0, stream, st, partials, nblocks, mode, prm, trace);
+    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(kRedBlock), 0, stream, st, partials, nblocks, gpart, ngpart, mode,
+                       prm, trace);
     return hipGetLastError();
 }
 

@@ -49,8 +49,9 @@ struct bfm_plan_s {
     size_t esz;
     AxisPlan ax[3];
     int red_blocks;
+    int gparts;   // partial sums of G written by the fused Poisson pass
     // workspace layout (byte offsets from the workspace base)
-    size_t off_state, off_trace, off_part, off_tables, off_pc, off_rho, off_f, total;
+    size_t off_state, off_trace, off_part, off_gpart, off_tables, off_pc, off_rho, off_f, total;
     size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
     std::vector<unsigned char> tables;         // host image of the spectral tables
 };
@@ -65,16 +66,16 @@ static bool is_2a3b(int n)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// FFT stage counts: n = 4^n4 2^n2 3^n3, packed as n4 | n2 << 8 | n3 << 16.
 static bool factor_radices(int n, uint32_t *code, int *nstages)
 {
-    int s = 0;
-    uint32_t c = 0;
-    while (n % 4 == 0) { c |= 0u << (2 * s); ++s; n /= 4; }
-    while (n % 2 == 0) { c |= 2u << (2 * s); ++s; n /= 2; }
-    while (n % 3 == 0) { c |= 3u << (2 * s); ++s; n /= 3; }
-    if (n != 1 || s > 16) return false;
-    *code = c;
-    *nstages = s;
+    uint32_t n4 = 0, n2 = 0, n3 = 0;
+    while (n % 4 == 0) { ++n4; n /= 4; }
+    while (n % 2 == 0) { ++n2; n /= 2; }
+    while (n % 3 == 0) { ++n3; n /= 3; }
+    if (n != 1) return false;
+    *code = n4 | (n2 << 8) | (n3 << 16);
+    *nstages = (int)(n4 + n2 + n3);
     return true;
 }
 
@@ -196,6 +197,8 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     P->off_state = off;  off = align256(off + sizeof(DevState));
     P->off_trace = off;  off = align256(off + sizeof(TraceRec) * kMaxTrace);
     P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * kMaxRedBlocks);
+    P->gparts = (int)dct_fused_parts(g.n[0], g.N, P->esz);
+    P->off_gpart = off;  off = align256(off + sizeof(double) * (size_t)P->gparts);
     P->off_tables = off; off = align256(off + P->tables.size());
     const size_t fb = align256((size_t)g.N * P->esz);
     P->off_pc = off;  off += fb;
@@ -221,6 +224,7 @@ struct Ws {
     DevState *st;
     TraceRec *trace;
     double *part;
+    double *gpart;
     unsigned char *tables;
     void *pc, *rho, *f;
     double *slot(int s) const { return part + (size_t)s * kMaxRedBlocks; }
@@ -236,6 +240,7 @@ static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
     w->st = (DevState *)(b + P->off_state);
     w->trace = (TraceRec *)(b + P->off_trace);
     w->part = (double *)(b + P->off_part);
+    w->gpart = (double *)(b + P->off_gpart);
     w->tables = b + P->off_tables;
     w->pc = b + P->off_pc;
     w->rho = b + P->off_rho;
@@ -263,11 +268,13 @@ static CtrlParams ctrl_params(bfm_plan P)
     return c;
 }
 
-// Poisson solve of f = a - b (b may be null) into `g_out`, G partials into
-// slot S_G.  With `update` non-null the last inverse pass writes
-// update = update + sigma * g instead of storing g.  The forward passes run
-// unconditionally of `done`; the inverse passes and the update are skipped
-// once the device stop flag is set (they run after the head controller).
+// Poisson solve of f = a - b (b may be null): forward transforms along the
+// contiguous (and, in 3D, middle) axes, then one pass along axis 0 that
+// transforms forward, divides by lambda (G partials into gpart) and
+// transforms back; `b` is cleared as it is consumed when zero_b is set.  The
+// remaining inverse passes run in poisson_inverse, the last one writing
+// update = update + sigma * g when `update` is non-null.  All passes are
+// no-ops once the device stop flag is set.
 template <typename T>
 static hipError_t poisson_forward(bfm_plan P, const Ws &w, const T *a, T *b, int zero_b, T *F,
                                   const int32_t *done, hipStream_t s)
@@ -275,17 +282,22 @@ static hipError_t poisson_forward(bfm_plan P, const Ws &w, const T *a, T *b, int
     const Grid &g = P->g;
     const int d = g.ndim;
     hipError_t e;
-    for (int ax = d - 1; ax >= 0; --ax) {
-        const T *src = ax == d - 1 ? a : F;
-        T *sub = ax == d - 1 ? b : nullptr;
-        e = launch_dct2_axis<T>(src, sub, F, P->ax[ax], g.N, ax == d - 1 ? zero_b : 0,
-                                w.tables + P->tab_tw[ax], w.tables + P->tab_qw[ax], done, s);
+    e = launch_dct_fwd<T>(a, b, F, P->ax[d - 1], g.N, zero_b, w.tables + P->tab_tw[d - 1],
+                          w.tables + P->tab_qw[d - 1], done, s);
+    if (e != hipSuccess) return e;
+    if (d == 3) {
+        e = launch_dct_fwd<T>(F, nullptr, F, P->ax[1], g.N, 0, w.tables + P->tab_tw[1], w.tables + P->tab_qw[1],
+                              done, s);
         if (e != hipSuccess) return e;
     }
     const T *l0 = (const T *)(w.tables + P->tab_lam[0]);
-    const T *l1 = (const T *)(w.tables + P->tab_lam[d > 1 ? 1 : 0]);
-    const T *l2 = (const T *)(w.tables + P->tab_lam[d > 2 ? 2 : 0]);
-    return launch_spectral_divide<T>(F, g, l0, l1, l2, w.slot(S_G), P->red_blocks, done, s);
+    const T *lA = (const T *)(w.tables + P->tab_lam[1]);
+    const T *lB = d == 3 ? (const T *)(w.tables + P->tab_lam[2]) : nullptr;
+    int np = 0;
+    e = launch_dct_fused<T>(F, P->ax[0], g.N, g.n[1], d == 3 ? g.n[2] : 1, w.tables + P->tab_tw[0],
+                            w.tables + P->tab_qw[0], l0, lA, lB, w.gpart, &np, done, s);
+    if (e == hipSuccess && np != P->gparts) return hipErrorInvalidValue;
+    return e;
 }
 
 template <typename T>
@@ -295,14 +307,14 @@ static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *upda
     const Grid &g = P->g;
     const int d = g.ndim;
     hipError_t e;
-    for (int ax = 0; ax < d; ++ax) {
-        const bool last = ax == d - 1;
-        T *dst = last ? (update != nullptr ? update : out) : F;
-        e = launch_dct3_axis<T>(F, dst, last ? update : nullptr, last && update ? &w.st->sigma : nullptr,
-                                P->ax[ax], g.N, w.tables + P->tab_tw[ax], w.tables + P->tab_qw[ax], done, s);
+    if (d == 3) {
+        e = launch_dct_inv<T>(F, F, nullptr, nullptr, P->ax[1], g.N, w.tables + P->tab_tw[1], w.tables + P->tab_qw[1],
+                              done, s);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    T *dst = update != nullptr ? update : out;
+    return launch_dct_inv<T>(F, dst, update, update != nullptr ? &w.st->sigma : nullptr, P->ax[d - 1], g.N,
+                             w.tables + P->tab_tw[d - 1], w.tables + P->tab_qw[d - 1], done, s);
 }
 
 // One half-step of Algorithm 1 on J(p) = <p, tgt> + <p^c, src>:
@@ -326,13 +338,13 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
         hipSuccess)
         return e;
     if ((e = poisson_forward<T>(P, w, tgt, rho, 1, F, done, s)) != hipSuccess) return e;
-    if ((e = launch_ctrl(w.st, w.part, nb, head_mode, cp, w.trace, s)) != hipSuccess) return e;
+    if ((e = launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, head_mode, cp, w.trace, s)) != hipSuccess) return e;
     if (head_only) return hipSuccess;
     if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
     if ((e = ctransform_field<T>(g, p, q, done, s)) != hipSuccess) return e;
     if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
         return e;
-    return launch_ctrl(w.st, w.part, nb, step_mode, cp, w.trace, s);
+    return launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, step_mode, cp, w.trace, s);
 }
 
 template <typename T>
@@ -345,7 +357,7 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
     DevState hs;
     HIP_TRY(upload_tables(P, w, s));
     HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, nb, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_INIT, cp, w.trace, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_INIT, cp, w.trace, s));
     HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hs.bad > 0) return fail(BFM_EINVAL, "mu/nu contain %.0f negative or non-finite values", hs.bad);
@@ -378,7 +390,7 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
         HIP_TRY(launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(pc, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_MEANS, cp, w.trace, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_MEANS, cp, w.trace, s));
     HIP_TRY(launch_shift_scale<T>(phi, phi, &w.st->mean_a, -1.0, psi, pc, &w.st->mean_a, 1.0, g.N, 1.0, s));
     HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -516,13 +528,12 @@ extern "C" bfm_status bfm_pushforward(bfm_plan plan, const void *phic, const voi
 template <typename T>
 static bfm_status poisson_impl(bfm_plan P, const T *f, T *g, double *G, const Ws &w, hipStream_t s)
 {
-    const int nb = P->red_blocks;
     HIP_TRY(upload_tables(P, w, s));
     HIP_TRY(poisson_forward<T>(P, w, f, nullptr, 0, g, nullptr, s));
     HIP_TRY(poisson_inverse<T>(P, w, g, g, nullptr, nullptr, s));
     if (G != nullptr) {
-        std::vector<double> h(nb);
-        HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_G), nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> h(P->gparts);
+        HIP_TRY(hipMemcpyAsync(h.data(), w.gpart, P->gparts * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *G = P->g.vol * host_slot_sum(h);
     }
@@ -549,7 +560,7 @@ static bfm_status grad_impl(bfm_plan P, const T *phi, const T *psi, double scale
     const int nb = P->red_blocks;
     HIP_TRY(launch_dot2<T>(psi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, CTRL_MEANS, ctrl_params(P), w.trace, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_MEANS, ctrl_params(P), w.trace, s));
     HIP_TRY(launch_shift_scale<T>(gmu, psi, &w.st->mean_a, -1.0, gnu, phi, &w.st->mean_b, -1.0, P->g.N,
                                   2.0 * P->g.vol * scale, s));
     return BFM_OK;
