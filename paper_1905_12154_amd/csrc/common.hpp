@@ -10,11 +10,12 @@ namespace bfm {
 
 constexpr int kWave = 64;
 constexpr int kRedBlock = 256;       // threads of every reduction-carrying kernel
-constexpr int kMaxRedBlocks = 1024;  // partial sums per reduction slot
+constexpr int kMaxRedBlocks = 1024;  // grid size of the grid-stride reduction kernels
 
 // Reduction slots: each kernel that contributes to a float64 sum writes one
-// partial per block into partials[slot * kMaxRedBlocks + block]; a single
-// controller block reduces them in a fixed order (deterministic).
+// partial per block into partials[slot * slot_len + block] (slot_len is a
+// property of the plan: at least the largest grid of a contributing kernel);
+// a single controller block reduces them in a fixed order (deterministic).
 enum Slot {
     S_P_TGT = 0,    // sum p * tgt            (head of a half-step)
     S_PC_SRC,       // sum p^c * src          (head)
@@ -42,6 +43,7 @@ struct DevState {
     double mass_mu, mass_nu, max_mu, max_nu, min_mu, min_nu, bad;
     double mean_a, mean_b;
     double dual_head, primal_head, G_head;   // last phi-step head
+    double q_src;                // sum q * src of the last step = sum p * tgt of the next head
     int32_t iter;                // completed full iterations
     int32_t done;                // 1: gap < tol reached, later kernels are no-ops
     int32_t nonfinite;           // 1: a non-finite scalar appeared

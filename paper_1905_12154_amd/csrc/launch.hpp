@@ -44,8 +44,9 @@ template <typename T>
 hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long long N, double *part1,
                        double *part2, int nblocks, const int32_t *done, hipStream_t stream);
 template <typename T>
-hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, int nblocks,
+hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, long long slot_len, int nblocks,
                         hipStream_t stream);
+long long splat_blocks(const Grid &g);
 template <typename T>
 hipError_t launch_fill(T *x, long long N, T value, hipStream_t stream);
 template <typename T>
@@ -62,12 +63,19 @@ enum CtrlMode {
     CTRL_STEP_PSI,     // I(psi_{n+1}), sigma update, iteration count
     CTRL_MEANS         // mean_a, mean_b from S_MEAN_A / S_MEAN_B
 };
+// Head modes OR'ed with this flag take sum p * tgt from the previous step's
+// sum q * src (the same products: p of a head is q of the step before it).
+constexpr int CTRL_REUSE_DOT = 0x100;
 
 struct CtrlParams {
     double tol, sigma0, sigma_min, beta1, beta2, alpha1, alpha2, vol, inv_N;
+    long long slot_len;   // stride between reduction slots
+    int nred;             // partials of the grid-stride kernels (dot products, statistics)
+    int nsplat;           // partials of the deposition kernel (S_PRIMAL, S_PC_SRC)
+    int ngpart;           // partials of G (separate array)
 };
 
-hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, const double *gpart, int ngpart,
-                       int mode, CtrlParams prm, TraceRec *trace, hipStream_t stream);
+hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,
+                       TraceRec *trace, hipStream_t stream);
 
 }  // namespace bfm

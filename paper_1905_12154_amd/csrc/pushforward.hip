@@ -9,78 +9,217 @@
 //     axis; T clamped to the box of cell centres [h/2, 1 - h/2];
 //   * T#mu with piecewise-multilinear test functions: the mass of cell x is
 //     split over the 2^d cell centres around T(x) with the multilinear
-//     weights (atomic adds; exact mass conservation up to rounding).
+//     weights (exact mass conservation up to rounding).
 // Fused float64 partial sums: sum mu |x - T|^2 / 2 (primal cost of the map)
 // and sum mu phi^c (the second term of J).
+//
+// Deposition: source cells are processed by compact tiles (32 x 32 in 2D,
+// 8 x 8 x 16 in 3D).  Where the map compresses mass, many sources of a tile
+// land on few target cells, and global atomics on the same addresses
+// serialise; so the workgroup first accumulates its deposits in an LDS box
+// covering all its targets (LDS atomics) and then adds each non-zero box
+// cell to the global density once.  Tiles whose targets spread over more
+// than the LDS box holds deposit with global atomics directly (no
+// contention there).
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace bfm {
 
+template <typename T> constexpr int box_cap() { return 8192 / (int)sizeof(T); }   // LDS box cells (8 KB)
+
+template <int D> struct Tile;
+template <> struct Tile<2> { static constexpr int s[2] = {32, 32}; static constexpr int cells = 1024; };
+template <> struct Tile<3> { static constexpr int s[3] = {8, 8, 16}; static constexpr int cells = 1024; };
+
+// Persistent workgroups walk the tiles in a grid-stride loop; a tile without
+// mass is skipped after one vote.  Partial sums are one per workgroup.
 template <typename T, int D>
 __global__ void __launch_bounds__(kRedBlock)
-splat_kernel(Grid g, const T *__restrict__ pc, const T *__restrict__ src, T *__restrict__ rho,
-             T *__restrict__ Tout, double *__restrict__ part_primal, double *__restrict__ part_pcsrc,
-             const int32_t *__restrict__ done)
+splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
+             T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
+             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done)
 {
     if (done != nullptr && *done) return;
+    constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
+    constexpr int kBoxCap = box_cap<T>();
     __shared__ double sh[kRedBlock / kWave];
+    __shared__ T box[kBoxCap];
+    __shared__ int bnd[2 * D];
+
+    int ntile[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
     double accP = 0.0, accJ = 0.0;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < g.N;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const T s = src[idx];
-        if (s == T(0) && Tout == nullptr) continue;   // no mass, nothing to write
-        int ii[D];
-        long long r = idx;
+
+    for (long long tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
+        int tc[D];
+        long long rem = tile;
 #pragma unroll
         for (int a = D - 1; a >= 0; --a) {
-            ii[a] = (int)(r % g.n[a]);
-            r /= g.n[a];
+            tc[a] = (int)(rem % ntile[a]);
+            rem /= ntile[a];
         }
-        const T p0 = pc[idx];
-        T wup[D];
-        long long base = 0;
-        T sq = T(0);
+        // source cells of this lane and their masses
+        long long idx[PER];
+        int ii[PER][D];
+        T s[PER];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            int r = threadIdx.x + q * kRedBlock;   // inside the tile, last axis fastest
+            bool inside = true;
+            long long id = 0;
+#pragma unroll
+            for (int a = D - 1; a >= 0; --a) {
+                ii[q][a] = tc[a] * Tile<D>::s[a] + r % Tile<D>::s[a];
+                r /= Tile<D>::s[a];
+                inside = inside && ii[q][a] < g.n[a];
+                id += (long long)ii[q][a] * g.stride[a];
+            }
+            idx[q] = inside ? id : -1;
+            s[q] = inside ? src[id] : T(0);
+            any = any || s[q] != T(0);
+        }
+        if (!__syncthreads_or(any) && Tout == nullptr) continue;
+        if (threadIdx.x < D) {
+            bnd[threadIdx.x] = 0x7fffffff;
+            bnd[D + threadIdx.x] = -1;
+        }
+        __syncthreads();
+
+        T wup[PER][D];
+        int lo[PER][D];
+        long long base[PER];
+        int bmin[D], bmax[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const int n = g.n[a];
-            const long long str = g.stride[a];
-            const int i = ii[a];
-            const T fn = T(n);
-            T d;
-            if (i == 0)
-                d = (pc[idx + str] - p0) * fn;
-            else if (i == n - 1)
-                d = (p0 - pc[idx - str]) * fn;
-            else
-                d = (pc[idx + str] - pc[idx - str]) * (T(0.5) * fn);
-            const T x = (T(i) + T(0.5)) / fn;
-            const T lo = T(0.5) / fn;
-            const T t = fmin(fmax(x - d, lo), T(1) - lo);
-            if (Tout != nullptr) Tout[(long long)a * g.N + idx] = t;
-            sq += (x - t) * (x - t);
-            const T q = t * fn - T(0.5);
-            int i0 = (int)floor(q);
-            i0 = min(max(i0, 0), n - 2);
-            wup[a] = q - T(i0);
-            base += (long long)i0 * str;
+            bmin[a] = 0x7fffffff;
+            bmax[a] = -1;
         }
-        if (s != T(0) && rho != nullptr) {
 #pragma unroll
-            for (int c = 0; c < (1 << D); ++c) {
-                T w = s;
-                long long off = base;
+        for (int q = 0; q < PER; ++q) {
+            if (idx[q] < 0 || (s[q] == T(0) && Tout == nullptr)) {
+                s[q] = T(0);
+                continue;
+            }
+            const long long id = idx[q];
+            const T p0 = pc[id];
+            T sq = T(0);
+            long long b = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int n = g.n[a];
+                const long long str = g.stride[a];
+                const int i = ii[q][a];
+                const T fn = T(n);
+                T d;
+                if (i == 0)
+                    d = (pc[id + str] - p0) * fn;
+                else if (i == n - 1)
+                    d = (p0 - pc[id - str]) * fn;
+                else
+                    d = (pc[id + str] - pc[id - str]) * (T(0.5) * fn);
+                const T x = (T(i) + T(0.5)) / fn;
+                const T lo_t = T(0.5) / fn;
+                const T t = fmin(fmax(x - d, lo_t), T(1) - lo_t);
+                if (Tout != nullptr) Tout[(long long)a * g.N + id] = t;
+                sq += (x - t) * (x - t);
+                const T qq = t * fn - T(0.5);
+                int i0 = (int)floor(qq);
+                i0 = min(max(i0, 0), n - 2);
+                wup[q][a] = qq - T(i0);
+                lo[q][a] = i0;
+                b += (long long)i0 * str;
+            }
+            base[q] = b;
+            if (s[q] != T(0) && rho != nullptr) {
+                accP += (double)s[q] * 0.5 * (double)sq;
+                accJ += (double)s[q] * (double)p0;
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    const int bit = (c >> (D - 1 - a)) & 1;
-                    w *= bit ? wup[a] : T(1) - wup[a];
-                    off += bit ? g.stride[a] : 0;
+                    bmin[a] = min(bmin[a], lo[q][a]);
+                    bmax[a] = max(bmax[a], lo[q][a] + 1);
                 }
-                atomicAdd(rho + off, w);
+            } else {
+                s[q] = T(0);
             }
-            accP += (double)s * 0.5 * (double)sq;
-            accJ += (double)s * (double)p0;
         }
+        // box bounds: reduce across the wave first, one LDS atomic per wave
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                bmin[a] = min(bmin[a], __shfl_xor(bmin[a], o, kWave));
+                bmax[a] = max(bmax[a], __shfl_xor(bmax[a], o, kWave));
+            }
+            if ((threadIdx.x & (kWave - 1)) == 0 && bmax[a] >= 0) {
+                atomicMin(&bnd[a], bmin[a]);
+                atomicMax(&bnd[D + a], bmax[a]);
+            }
+        }
+        __syncthreads();
+        if (rho == nullptr || bnd[D] < 0) continue;   // uniform: read after the barrier
+        int bl[D], bs[D];
+        long long area = 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            bl[a] = bnd[a];
+            bs[a] = bnd[D + a] - bnd[a] + 1;
+            area *= bs[a];
+        }
+        if (area <= kBoxCap) {
+            for (int e = threadIdx.x; e < area; e += kRedBlock) box[e] = T(0);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (s[q] == T(0)) continue;
+#pragma unroll
+                for (int c = 0; c < (1 << D); ++c) {
+                    T w = s[q];
+                    int off = 0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const int bit = (c >> (D - 1 - a)) & 1;
+                        w *= bit ? wup[q][a] : T(1) - wup[q][a];
+                        off = off * bs[a] + (lo[q][a] + bit - bl[a]);
+                    }
+                    atomicAdd(&box[off], w);
+                }
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < area; e += kRedBlock) {
+                const T v = box[e];
+                if (v != T(0)) {
+                    int r = e;
+                    long long gi = 0;
+#pragma unroll
+                    for (int a = D - 1; a >= 0; --a) {
+                        gi += (long long)(bl[a] + r % bs[a]) * g.stride[a];
+                        r /= bs[a];
+                    }
+                    atomicAdd(rho + gi, v);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (s[q] == T(0)) continue;
+#pragma unroll
+                for (int c = 0; c < (1 << D); ++c) {
+                    T w = s[q];
+                    long long off = base[q];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const int bit = (c >> (D - 1 - a)) & 1;
+                        w *= bit ? wup[q][a] : T(1) - wup[q][a];
+                        off += bit ? g.stride[a] : 0;
+                    }
+                    atomicAdd(rho + off, w);
+                }
+            }
+        }
+        __syncthreads();   // box and bnd are reused by the next tile
     }
     const double P = block_reduce<R_SUM>(accP, sh);
     const double J = block_reduce<R_SUM>(accJ, sh);
@@ -90,16 +229,31 @@ splat_kernel(Grid g, const T *__restrict__ pc, const T *__restrict__ src, T *__r
     }
 }
 
+template <int D> long long splat_tiles(const Grid &g) {
+    long long t = 1;
+    for (int a = 0; a < D; ++a) t *= (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
+    return t;
+}
+
+static long long splat_ntiles(const Grid &g) { return g.ndim == 2 ? splat_tiles<2>(g) : splat_tiles<3>(g); }
+
+// Workgroups of the deposition kernel: one per tile up to 2048 (eight per CU).
+long long splat_blocks(const Grid &g) {
+    const long long t = splat_ntiles(g);
+    return t < 2048 ? t : 2048;
+}
+
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream)
+                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream)
 {
+    const long long nb = splat_blocks(g), nt = splat_ntiles(g);
     if (g.ndim == 2)
-        hipLaunchKernelGGL((splat_kernel<T, 2>), dim3(nblocks), dim3(kRedBlock), 0, stream, g, pc, src, rho,
-                           Tout, part_primal, part_pcsrc, done);
+        hipLaunchKernelGGL((splat_kernel<T, 2>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
+                           rho, Tout, part_primal, part_pcsrc, done);
     else if (g.ndim == 3)
-        hipLaunchKernelGGL((splat_kernel<T, 3>), dim3(nblocks), dim3(kRedBlock), 0, stream, g, pc, src, rho,
-                           Tout, part_primal, part_pcsrc, done);
+        hipLaunchKernelGGL((splat_kernel<T, 3>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
+                           rho, Tout, part_primal, part_pcsrc, done);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -8,6 +8,8 @@
 // gradient step: with increase = J(p + sigma g) - J(p) and G = ||grad||^2_{H^1},
 // keep sigma when beta1 sigma G <= increase <= beta2 sigma G, otherwise
 // shrink by alpha2 (not below sigma_min) or grow by alpha1; no backtracking.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -22,10 +24,34 @@ dot2_kernel(const T *__restrict__ a1, const T *__restrict__ b1, const T *__restr
     if (done != nullptr && *done) return;
     __shared__ double sh[kRedBlock / kWave];
     double s1 = 0.0, s2 = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-         i += (long long)gridDim.x * blockDim.x) {
-        s1 += (double)a1[i] * (b1 != nullptr ? (double)b1[i] : 1.0);
-        if (a2 != nullptr) s2 += (double)a2[i] * (double)b2[i];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool vec = (N & 3) == 0 && ((((uintptr_t)a1 | (uintptr_t)(b1 ? b1 : a1) | (uintptr_t)(a2 ? a2 : a1) |
+                                        (uintptr_t)(b2 ? b2 : a1)) & 15) == 0);
+    if (vec) {
+        using V = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+        const long long N4 = N / 4;
+        for (long long i = t0; i < N4; i += stride) {
+            const V x = reinterpret_cast<const V *>(a1)[i];
+            if (b1 != nullptr) {
+                const V y = reinterpret_cast<const V *>(b1)[i];
+                s1 += (double)x.x * (double)y.x + (double)x.y * (double)y.y + (double)x.z * (double)y.z +
+                      (double)x.w * (double)y.w;
+            } else {
+                s1 += (double)x.x + (double)x.y + (double)x.z + (double)x.w;
+            }
+            if (a2 != nullptr) {
+                const V u = reinterpret_cast<const V *>(a2)[i];
+                const V v = reinterpret_cast<const V *>(b2)[i];
+                s2 += (double)u.x * (double)v.x + (double)u.y * (double)v.y + (double)u.z * (double)v.z +
+                      (double)u.w * (double)v.w;
+            }
+        }
+    } else {
+        for (long long i = t0; i < N; i += stride) {
+            s1 += (double)a1[i] * (b1 != nullptr ? (double)b1[i] : 1.0);
+            if (a2 != nullptr) s2 += (double)a2[i] * (double)b2[i];
+        }
     }
     s1 = block_reduce<R_SUM>(s1, sh);
     if (threadIdx.x == 0) part1[blockIdx.x] = s1;
@@ -47,7 +73,8 @@ hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long 
 // Sums, extrema and a count of invalid (negative or non-finite) values of mu, nu.
 template <typename T>
 __global__ void __launch_bounds__(kRedBlock)
-stats_kernel(const T *__restrict__ mu, const T *__restrict__ nu, long long N, double *__restrict__ partials)
+stats_kernel(const T *__restrict__ mu, const T *__restrict__ nu, long long N, double *__restrict__ partials,
+             long long slot_len)
 {
     __shared__ double sh[kRedBlock / kWave];
     double smu = 0, snu = 0, xmu = -INFINITY, xnu = -INFINITY, nmu = INFINITY, nnu = INFINITY, bad = 0;
@@ -72,20 +99,21 @@ stats_kernel(const T *__restrict__ mu, const T *__restrict__ nu, long long N, do
     const double r6 = block_reduce<R_SUM>(bad, sh);
     if (threadIdx.x == 0) {
         const int b = blockIdx.x;
-        partials[S_SUM_MU * kMaxRedBlocks + b] = r0;
-        partials[S_SUM_NU * kMaxRedBlocks + b] = r1;
-        partials[S_MAX_MU * kMaxRedBlocks + b] = r2;
-        partials[S_MAX_NU * kMaxRedBlocks + b] = r3;
-        partials[S_MIN_MU * kMaxRedBlocks + b] = r4;
-        partials[S_MIN_NU * kMaxRedBlocks + b] = r5;
-        partials[S_BAD * kMaxRedBlocks + b] = r6;
+        partials[S_SUM_MU * slot_len + b] = r0;
+        partials[S_SUM_NU * slot_len + b] = r1;
+        partials[S_MAX_MU * slot_len + b] = r2;
+        partials[S_MAX_NU * slot_len + b] = r3;
+        partials[S_MIN_MU * slot_len + b] = r4;
+        partials[S_MIN_NU * slot_len + b] = r5;
+        partials[S_BAD * slot_len + b] = r6;
     }
 }
 
 template <typename T>
-hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, int nblocks, hipStream_t stream)
+hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, long long slot_len, int nblocks,
+                        hipStream_t stream)
 {
-    hipLaunchKernelGGL((stats_kernel<T>), dim3(nblocks), dim3(kRedBlock), 0, stream, mu, nu, N, partials);
+    hipLaunchKernelGGL((stats_kernel<T>), dim3(nblocks), dim3(kRedBlock), 0, stream, mu, nu, N, partials, slot_len);
     return hipGetLastError();
 }
 
@@ -132,22 +160,22 @@ hipError_t launch_shift_scale(T *out_a, const T *in_a, const double *shift_a, do
     return hipGetLastError();
 }
 
-__device__ double slot_reduce_sum(const double *partials, int slot, int nb, double *sh)
+__device__ double slot_reduce_sum(const double *partials, long long slot_len, int slot, int nb, double *sh)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[slot * kMaxRedBlocks + i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[slot * slot_len + i];
     return block_reduce<R_SUM>(v, sh);
 }
-__device__ double slot_reduce_max(const double *partials, int slot, int nb, double *sh)
+__device__ double slot_reduce_max(const double *partials, long long slot_len, int slot, int nb, double *sh)
 {
     double v = -INFINITY;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, partials[slot * kMaxRedBlocks + i]);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmax(v, partials[slot * slot_len + i]);
     return block_reduce<R_MAX>(v, sh);
 }
-__device__ double slot_reduce_min(const double *partials, int slot, int nb, double *sh)
+__device__ double slot_reduce_min(const double *partials, long long slot_len, int slot, int nb, double *sh)
 {
     double v = INFINITY;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmin(v, partials[slot * kMaxRedBlocks + i]);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v = fmin(v, partials[slot * slot_len + i]);
     return block_reduce<R_MIN>(v, sh);
 }
 
@@ -159,18 +187,22 @@ __device__ double step_rule(double sigma, double increase, double G, const CtrlP
 }
 
 __global__ void __launch_bounds__(kRedBlock)
-ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const double *__restrict__ gpart, int ng,
-            int mode, CtrlParams prm, TraceRec *trace)
+ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__restrict__ gpart, int mode,
+            CtrlParams prm, TraceRec *trace)
 {
     __shared__ double sh[kRedBlock / kWave];
+    const int nb = prm.nred, ns = prm.nsplat, ng = prm.ngpart;
+    const long long sl = prm.slot_len;
+    const bool reuse_dot = (mode & CTRL_REUSE_DOT) != 0;
+    mode &= 0xff;
     if (mode == CTRL_INIT) {
-        const double smu = slot_reduce_sum(partials, S_SUM_MU, nb, sh);
-        const double snu = slot_reduce_sum(partials, S_SUM_NU, nb, sh);
-        const double xmu = slot_reduce_max(partials, S_MAX_MU, nb, sh);
-        const double xnu = slot_reduce_max(partials, S_MAX_NU, nb, sh);
-        const double nmu = slot_reduce_min(partials, S_MIN_MU, nb, sh);
-        const double nnu = slot_reduce_min(partials, S_MIN_NU, nb, sh);
-        const double bad = slot_reduce_sum(partials, S_BAD, nb, sh);
+        const double smu = slot_reduce_sum(partials, sl, S_SUM_MU, nb, sh);
+        const double snu = slot_reduce_sum(partials, sl, S_SUM_NU, nb, sh);
+        const double xmu = slot_reduce_max(partials, sl, S_MAX_MU, nb, sh);
+        const double xnu = slot_reduce_max(partials, sl, S_MAX_NU, nb, sh);
+        const double nmu = slot_reduce_min(partials, sl, S_MIN_MU, nb, sh);
+        const double nnu = slot_reduce_min(partials, sl, S_MIN_NU, nb, sh);
+        const double bad = slot_reduce_sum(partials, sl, S_BAD, nb, sh);
         if (threadIdx.x == 0) {
             st->mass_mu = prm.vol * smu;
             st->mass_nu = prm.vol * snu;
@@ -191,8 +223,8 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const dou
         return;
     }
     if (mode == CTRL_MEANS) {
-        const double a = slot_reduce_sum(partials, S_MEAN_A, nb, sh);
-        const double b = slot_reduce_sum(partials, S_MEAN_B, nb, sh);
+        const double a = slot_reduce_sum(partials, sl, S_MEAN_A, nb, sh);
+        const double b = slot_reduce_sum(partials, sl, S_MEAN_B, nb, sh);
         if (threadIdx.x == 0) {
             st->mean_a = a * prm.inv_N;
             st->mean_b = b * prm.inv_N;
@@ -201,9 +233,9 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const dou
     }
     if (st->done) return;
     if (mode == CTRL_HEAD_PHI || mode == CTRL_HEAD_PSI) {
-        const double a = slot_reduce_sum(partials, S_P_TGT, nb, sh);
-        const double b = slot_reduce_sum(partials, S_PC_SRC, nb, sh);
-        const double P = slot_reduce_sum(partials, S_PRIMAL, nb, sh);
+        const double a = reuse_dot ? st->q_src : slot_reduce_sum(partials, sl, S_P_TGT, nb, sh);
+        const double b = slot_reduce_sum(partials, sl, S_PC_SRC, ns, sh);
+        const double P = slot_reduce_sum(partials, sl, S_PRIMAL, ns, sh);
         double gv = 0.0;
         for (int i = threadIdx.x; i < ng; i += blockDim.x) gv += gpart[i];
         const double G = block_reduce<R_SUM>(gv, sh);
@@ -239,9 +271,10 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const dou
         return;
     }
     if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
-        const double a = slot_reduce_sum(partials, S_Q_TGT, nb, sh);
-        const double b = slot_reduce_sum(partials, S_Q_SRC, nb, sh);
+        const double a = slot_reduce_sum(partials, sl, S_Q_TGT, nb, sh);
+        const double b = slot_reduce_sum(partials, sl, S_Q_SRC, nb, sh);
         if (threadIdx.x == 0) {
+            st->q_src = b;
             st->J_new = prm.vol * (a + b);
             if (!isfinite(st->J_new)) {
                 st->nonfinite = 1;
@@ -261,18 +294,17 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, int nb, const dou
     }
 }
 
-hipError_t launch_ctrl(DevState *st, const double *partials, int nblocks, const double *gpart, int ngpart,
-                       int mode, CtrlParams prm, TraceRec *trace, hipStream_t stream)
+hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,
+                       TraceRec *trace, hipStream_t stream)
 {
-    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(kRedBlock), 0, stream, st, partials, nblocks, gpart, ngpart, mode,
-                       prm, trace);
+    hipLaunchKernelGGL(ctrl_kernel, dim3(1), dim3(kRedBlock), 0, stream, st, partials, gpart, mode, prm, trace);
     return hipGetLastError();
 }
 
 #define BFM_INST_RED(T)                                                                                      \
     template hipError_t launch_dot2<T>(const T *, const T *, const T *, const T *, long long, double *,      \
                                        double *, int, const int32_t *, hipStream_t);                         \
-    template hipError_t launch_stats<T>(const T *, const T *, long long, double *, int, hipStream_t);        \
+    template hipError_t launch_stats<T>(const T *, const T *, long long, double *, long long, int, hipStream_t); \
     template hipError_t launch_fill<T>(T *, long long, T, hipStream_t);                                      \
     template hipError_t launch_shift_scale<T>(T *, const T *, const double *, double, T *, const T *,       \
                                               const double *, double, long long, double, hipStream_t);

@@ -49,7 +49,9 @@ struct bfm_plan_s {
     size_t esz;
     AxisPlan ax[3];
     int red_blocks;
-    int gparts;   // partial sums of G written by the fused Poisson pass
+    int gparts;      // partial sums of G written by the fused Poisson pass
+    int nsplat;      // workgroups of the deposition kernel
+    long long slot_len;
     // workspace layout (byte offsets from the workspace base)
     size_t off_state, off_trace, off_part, off_gpart, off_tables, off_pc, off_rho, off_f, total;
     size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
@@ -196,7 +198,9 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     size_t off = 0;
     P->off_state = off;  off = align256(off + sizeof(DevState));
     P->off_trace = off;  off = align256(off + sizeof(TraceRec) * kMaxTrace);
-    P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * kMaxRedBlocks);
+    P->nsplat = (int)splat_blocks(g);
+    P->slot_len = P->nsplat > kMaxRedBlocks ? P->nsplat : kMaxRedBlocks;
+    P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * (size_t)P->slot_len);
     P->gparts = (int)dct_fused_parts(g.n[0], g.N, P->esz);
     P->off_gpart = off;  off = align256(off + sizeof(double) * (size_t)P->gparts);
     P->off_tables = off; off = align256(off + P->tables.size());
@@ -227,7 +231,8 @@ struct Ws {
     double *gpart;
     unsigned char *tables;
     void *pc, *rho, *f;
-    double *slot(int s) const { return part + (size_t)s * kMaxRedBlocks; }
+    long long slot_len;
+    double *slot(int s) const { return part + (size_t)s * slot_len; }
 };
 
 static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
@@ -241,6 +246,7 @@ static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
     w->trace = (TraceRec *)(b + P->off_trace);
     w->part = (double *)(b + P->off_part);
     w->gpart = (double *)(b + P->off_gpart);
+    w->slot_len = P->slot_len;
     w->tables = b + P->off_tables;
     w->pc = b + P->off_pc;
     w->rho = b + P->off_rho;
@@ -265,6 +271,10 @@ static CtrlParams ctrl_params(bfm_plan P)
     c.alpha2 = P->prm.alpha2;
     c.vol = P->g.vol;
     c.inv_N = 1.0 / (double)P->g.N;
+    c.slot_len = P->slot_len;
+    c.nred = P->red_blocks;
+    c.nsplat = P->nsplat;
+    c.ngpart = P->gparts;
     return c;
 }
 
@@ -323,7 +333,7 @@ static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *upda
 //   step:  p <- p + sigma g, q = p^c, J(p), controller `step_mode`.
 template <typename T>
 static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T *tgt, T *q, int head_mode,
-                            int step_mode, bool head_only, hipStream_t s)
+                            int step_mode, bool head_only, bool head_dot, hipStream_t s)
 {
     const Grid &g = P->g;
     const int32_t *done = &w.st->done;
@@ -332,19 +342,22 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     const CtrlParams cp = ctrl_params(P);
     hipError_t e;
     if ((e = ctransform_field<T>(g, p, pc, done, s)) != hipSuccess) return e;
-    if ((e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
+    if (head_dot &&
+        (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
     if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, done, s)) !=
         hipSuccess)
         return e;
     if ((e = poisson_forward<T>(P, w, tgt, rho, 1, F, done, s)) != hipSuccess) return e;
-    if ((e = launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, head_mode, cp, w.trace, s)) != hipSuccess) return e;
+    if ((e = launch_ctrl(w.st, w.part, w.gpart, head_mode | (head_dot ? 0 : CTRL_REUSE_DOT), cp, w.trace, s)) !=
+        hipSuccess)
+        return e;
     if (head_only) return hipSuccess;
     if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
     if ((e = ctransform_field<T>(g, p, q, done, s)) != hipSuccess) return e;
     if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
         return e;
-    return launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, step_mode, cp, w.trace, s);
+    return launch_ctrl(w.st, w.part, w.gpart, step_mode, cp, w.trace, s);
 }
 
 template <typename T>
@@ -356,8 +369,8 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
     const CtrlParams cp = ctrl_params(P);
     DevState hs;
     HIP_TRY(upload_tables(P, w, s));
-    HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, nb, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_INIT, cp, w.trace, s));
+    HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, P->slot_len, nb, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_INIT, cp, w.trace, s));
     HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hs.bad > 0) return fail(BFM_EINVAL, "mu/nu contain %.0f negative or non-finite values", hs.bad);
@@ -375,9 +388,9 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
     const int K = P->prm.check_every;
     for (int it = 0; it <= P->prm.max_iters; ++it) {
         const bool last = it == P->prm.max_iters;
-        HIP_TRY(half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, last, s));
+        HIP_TRY(half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, last, it == 0, s));
         if (last) break;
-        HIP_TRY(half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, s));
+        HIP_TRY(half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, false, s));
         if ((it + 1) % K == 0) {
             HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
@@ -390,7 +403,7 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
         HIP_TRY(launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(pc, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_MEANS, cp, w.trace, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_MEANS, cp, w.trace, s));
     HIP_TRY(launch_shift_scale<T>(phi, phi, &w.st->mean_a, -1.0, psi, pc, &w.st->mean_a, 1.0, g.N, 1.0, s));
     HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -501,8 +514,8 @@ static bfm_status push_impl(bfm_plan P, const T *phic, const T *mass, T *rho, T 
     HIP_TRY(launch_fill<T>(rho, P->g.N, T(0), s));
     HIP_TRY(launch_splat<T>(P->g, phic, mass, rho, Tmap, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, nullptr, s));
     if (primal != nullptr) {
-        std::vector<double> h(nb);
-        HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_PRIMAL), nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> h(P->nsplat);
+        HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_PRIMAL), P->nsplat * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *primal = P->g.vol * host_slot_sum(h);
     }
@@ -560,7 +573,7 @@ static bfm_status grad_impl(bfm_plan P, const T *phi, const T *psi, double scale
     const int nb = P->red_blocks;
     HIP_TRY(launch_dot2<T>(psi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
     HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, P->g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, nb, w.gpart, P->gparts, CTRL_MEANS, ctrl_params(P), w.trace, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_MEANS, ctrl_params(P), w.trace, s));
     HIP_TRY(launch_shift_scale<T>(gmu, psi, &w.st->mean_a, -1.0, gnu, phi, &w.st->mean_b, -1.0, P->g.N,
                                   2.0 * P->g.vol * scale, s));
     return BFM_OK;
