@@ -112,6 +112,23 @@ bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *
                      void *phi, void *psi, void *T, void *workspace, size_t ws_bytes,
                      void *stream, bfm_result *result);
 
+/* Batched solve of `npairs` independent problems (Algorithm 1 for each),
+ * advanced together: after the first iteration, iters_per_graph iterations of
+ * every problem are captured once into a HIP graph (independent problems on
+ * parallel branches) and the graph is replayed; each problem keeps its own
+ * step size, gap and stop flag, and a problem that has stopped turns into
+ * no-ops.  Stop flags are read on the host between replays.
+ *   plans       npairs plans (any shapes; same dtype and max_iters; tol may differ).
+ *   mu .. T     host arrays of npairs device pointers (T may be NULL, or
+ *               hold NULL entries); same meaning as in bfm_solve.
+ *   workspaces  host array of npairs distinct device workspaces;
+ *   ws_bytes    their sizes.
+ *   results     host array of npairs reports (may be NULL).
+ * Synchronises `stream` between graph replays and at the end. */
+bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *const *mu, const void *const *nu,
+                             void *const *phi, void *const *psi, void *const *T, void *const *workspaces,
+                             const size_t *ws_bytes, int32_t iters_per_graph, void *stream, bfm_result *results);
+
 /* Primitive: quadratic-cost c-transform on the grid (Definition of the
  * c-transform; separable evaluation of Section 4.1; per line the Legendre
  * transform on the lower convex hull, eq. legendre / legendre_search):

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
                 5: "BFM_EUNSUPPORTED"}
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
-            "bfm_version", "bfm_ctransform_axis", "bfm_trace"]
+            "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched"]
 
 
 class BFMError(RuntimeError):
@@ -75,6 +75,8 @@ def lib():
         L.bfm_poisson_neumann.argtypes = [vp, vp, vp, P(dbl), vp, sz, vp]
         L.bfm_grad.argtypes = [vp, vp, vp, dbl, vp, vp, vp, sz, vp]
         L.bfm_ctransform_axis.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
+                                        P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
         L.bfm_last_error.argtypes = []
         L.bfm_last_error.restype = ctypes.c_char_p
@@ -287,6 +289,78 @@ def pushforward(phic: torch.Tensor, mass: torch.Tensor, return_map=True):
 
 def poisson_neumann(f: torch.Tensor):
     return plan_for(f.shape, f.dtype).poisson_neumann(f)
+
+
+def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_iters: int = 100,
+                  tol: float = 0.0, iters_per_graph: int = 8, return_map: bool = False,
+                  workspaces: Optional[List[torch.Tensor]] = None) -> List[SolveResult]:
+    """Solve many independent problems together (``bfm_solve_batched``): one
+    HIP graph replay advances every problem by ``iters_per_graph`` iterations.
+    Problems may have different shapes; all share dtype and ``max_iters``."""
+    n = len(mus)
+    if n != len(nus) or n == 0:
+        raise ValueError("need the same positive number of mu and nu tensors")
+    dev = mus[0].device
+    plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol) for m in mus]
+    mus = [p._field(m, "mu[%d]" % i) for i, (p, m) in enumerate(zip(plans, mus))]
+    nus = [p._field(v, "nu[%d]" % i) for i, (p, v) in enumerate(zip(plans, nus))]
+    phis = [torch.empty_like(m) for m in mus]
+    psis = [torch.empty_like(m) for m in mus]
+    Ts = [torch.empty((len(p.shape),) + p.shape, dtype=p.dtype, device=dev) for p in plans] if return_map else None
+    if workspaces is None:
+        workspaces = [torch.empty(p.ws_bytes + 256, dtype=torch.uint8, device=dev) for p in plans]
+    ws = []
+    for p, raw in zip(plans, workspaces):
+        off = (-raw.data_ptr()) % 256
+        ws.append(raw[off:off + p.ws_bytes])
+    VP = ctypes.c_void_p * n
+    res = (Result * n)()
+    _check(lib().bfm_solve_batched(
+        n, VP(*[p.handle.value for p in plans]), VP(*[m.data_ptr() for m in mus]), VP(*[v.data_ptr() for v in nus]),
+        VP(*[t.data_ptr() for t in phis]), VP(*[t.data_ptr() for t in psis]),
+        VP(*[t.data_ptr() for t in Ts]) if Ts is not None else None, VP(*[w.data_ptr() for w in ws]),
+        (ctypes.c_size_t * n)(*[p.ws_bytes for p in plans]), int(iters_per_graph), _stream(dev), res))
+    out = []
+    for i in range(n):
+        r = res[i]
+        out.append(SolveResult(phi=phis[i], psi=psis[i], T=Ts[i] if Ts is not None else None, dual=r.dual,
+                               primal=r.primal, gap=r.gap, G=r.G, sigma=r.sigma, iters=r.iters,
+                               converged=bool(r.converged), mass_mu=r.mass_mu, mass_nu=r.mass_nu))
+    return out
+
+
+class W2LossBatched(torch.autograd.Function):
+    """W2^2 of many (mu_i, nu_i) pairs from one batched solve; the backward
+    pass returns each pair's mean-zeroed potentials times 2 cell_volume."""
+
+    @staticmethod
+    def forward(ctx, max_iters, tol, iters_per_graph, *tensors):
+        n = len(tensors) // 2
+        mus, nus = tensors[:n], tensors[n:]
+        rs = solve_batched([m.detach() for m in mus], [v.detach() for v in nus], max_iters=max_iters, tol=tol,
+                           iters_per_graph=iters_per_graph)
+        ctx.plans = [plan_for(m.shape, m.dtype) for m in mus]
+        ctx.save_for_backward(*[r.phi for r in rs], *[r.psi for r in rs])
+        ctx.results = [(r.iters, r.converged, r.gap) for r in rs]
+        return torch.tensor([r.w2sq for r in rs], dtype=mus[0].dtype, device=mus[0].device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        saved = ctx.saved_tensors
+        n = len(saved) // 2
+        go = grad_out.detach().double().cpu().tolist()
+        gmus, gnus = [], []
+        for i in range(n):
+            gmu, gnu = ctx.plans[i].grad(saved[i], saved[n + i], go[i])
+            gmus.append(gmu)
+            gnus.append(gnu)
+        return (None, None, None, *gmus, *gnus)
+
+
+def w2_loss_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_iters: int = 200,
+                    tol: float = 1e-6, iters_per_graph: int = 8) -> torch.Tensor:
+    """Vector of W2^2 values, differentiable w.r.t. every mu_i and nu_i."""
+    return W2LossBatched.apply(max_iters, tol, iters_per_graph, *mus, *nus)
 
 
 class W2Loss(torch.autograd.Function):

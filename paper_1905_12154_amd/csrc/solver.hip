@@ -278,6 +278,16 @@ static CtrlParams ctrl_params(bfm_plan P)
     return c;
 }
 
+static bfm_status check_inputs(const DevState &hs)
+{
+    if (hs.bad > 0) return fail(BFM_EINVAL, "mu/nu contain %.0f negative or non-finite values", hs.bad);
+    if (fabs(hs.mass_mu - 1.0) > 1e-5 || fabs(hs.mass_nu - 1.0) > 1e-5)
+        return fail(BFM_EINVAL, "densities must have unit mass (cell_volume*sum): mu %.9g, nu %.9g", hs.mass_mu,
+                    hs.mass_nu);
+    if (!(hs.max_mu > 0.0) || !(hs.max_nu > 0.0)) return fail(BFM_EINVAL, "a density is identically zero");
+    return BFM_OK;
+}
+
 // Poisson solve of f = a - b (b may be null): forward transforms along the
 // contiguous (and, in 3D, middle) axes, then one pass along axis 0 that
 // transforms forward, divides by lambda (G partials into gpart) and
@@ -360,53 +370,78 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     return launch_ctrl(w.st, w.part, w.gpart, step_mode, cp, w.trace, s);
 }
 
+// Solve in four parts so that the iterations can be enqueued without any host
+// synchronisation (and captured in a graph):
+//   begin:   tables, input statistics, sigma0, validation (synchronises),
+//            rho = 0, phi = phi_init or 0;
+//   iterate: full iterations it0 .. it0+count-1 (the head of iteration 0
+//            computes <phi, nu>, later heads reuse the previous step's sum);
+//   final:   the head of iteration `it` only (no-op once the stop flag is set);
+//   finish:  T from the last head's phi^c, phi - mean, psi = phi^c + mean,
+//            the result block (synchronises).
 template <typename T>
-static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_init, T *phi, T *psi, T *Tmap,
-                             const Ws &w, hipStream_t s, bfm_result *res)
+static bfm_status solve_begin(bfm_plan P, const T *mu, const T *nu, const T *phi_init, T *phi, const Ws &w,
+                              hipStream_t s, bool sync_check)
 {
     const Grid &g = P->g;
-    const int nb = P->red_blocks;
-    const CtrlParams cp = ctrl_params(P);
-    DevState hs;
     HIP_TRY(upload_tables(P, w, s));
-    HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, P->slot_len, nb, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_INIT, cp, w.trace, s));
-    HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hs.bad > 0) return fail(BFM_EINVAL, "mu/nu contain %.0f negative or non-finite values", hs.bad);
-    if (fabs(hs.mass_mu - 1.0) > 1e-5 || fabs(hs.mass_nu - 1.0) > 1e-5)
-        return fail(BFM_EINVAL, "densities must have unit mass (cell_volume*sum): mu %.9g, nu %.9g", hs.mass_mu,
-                    hs.mass_nu);
-    if (!(hs.max_mu > 0.0) || !(hs.max_nu > 0.0)) return fail(BFM_EINVAL, "a density is identically zero");
-
+    HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, P->slot_len, P->red_blocks, s));
+    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_INIT, ctrl_params(P), w.trace, s));
     HIP_TRY(launch_fill<T>((T *)w.rho, g.N, T(0), s));
     if (phi_init != nullptr)
         HIP_TRY(hipMemcpyAsync(phi, phi_init, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s));
     else
         HIP_TRY(launch_fill<T>(phi, g.N, T(0), s));
-
-    const int K = P->prm.check_every;
-    for (int it = 0; it <= P->prm.max_iters; ++it) {
-        const bool last = it == P->prm.max_iters;
-        HIP_TRY(half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, last, it == 0, s));
-        if (last) break;
-        HIP_TRY(half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, false, s));
-        if ((it + 1) % K == 0) {
-            HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (hs.done) break;
-        }
-    }
-    // final outputs: T from the last head's phi^c, phi - mean, psi = phi^c + mean
-    T *pc = (T *)w.pc;
-    if (Tmap != nullptr)
-        HIP_TRY(launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s));
-    HIP_TRY(launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_dot2<T>(pc, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s));
-    HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_MEANS, cp, w.trace, s));
-    HIP_TRY(launch_shift_scale<T>(phi, phi, &w.st->mean_a, -1.0, psi, pc, &w.st->mean_a, 1.0, g.N, 1.0, s));
+    if (!sync_check) return BFM_OK;
+    DevState hs;
     HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return check_inputs(hs);
+}
+
+template <typename T>
+static hipError_t enqueue_iterations(bfm_plan P, const Ws &w, const T *mu, const T *nu, T *phi, T *psi, int it0,
+                                     int count, hipStream_t s)
+{
+    hipError_t e;
+    for (int it = it0; it < it0 + count; ++it) {
+        if ((e = half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, it == 0, s)) != hipSuccess)
+            return e;
+        if ((e = half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, false, s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+static hipError_t enqueue_final_head(bfm_plan P, const Ws &w, const T *mu, const T *nu, T *phi, T *psi, int it,
+                                     hipStream_t s)
+{
+    return half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, true, it == 0, s);
+}
+
+template <typename T>
+static hipError_t enqueue_finish(bfm_plan P, const Ws &w, const T *mu, T *phi, T *psi, T *Tmap, hipStream_t s)
+{
+    const Grid &g = P->g;
+    const int nb = P->red_blocks;
+    T *pc = (T *)w.pc;
+    hipError_t e;
+    if (Tmap != nullptr &&
+        (e = launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s)) != hipSuccess)
+        return e;
+    if ((e = launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_dot2<T>(pc, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_B), nullptr, nb, nullptr, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_ctrl(w.st, w.part, w.gpart, CTRL_MEANS, ctrl_params(P), w.trace, s)) != hipSuccess) return e;
+    return launch_shift_scale<T>(phi, phi, &w.st->mean_a, -1.0, psi, pc, &w.st->mean_a, 1.0, g.N, 1.0, s);
+}
+
+static bfm_status fill_result(const DevState &hs, bfm_result *res)
+{
     if (res != nullptr) {
         memset(res, 0, sizeof(*res));
         res->iters = hs.iter;
@@ -422,6 +457,30 @@ static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_
     }
     if (hs.nonfinite) return fail(BFM_ENUMERIC, "non-finite value in the dual, primal or gradient norm");
     return BFM_OK;
+}
+
+template <typename T>
+static bfm_status solve_impl(bfm_plan P, const T *mu, const T *nu, const T *phi_init, T *phi, T *psi, T *Tmap,
+                             const Ws &w, hipStream_t s, bfm_result *res)
+{
+    bfm_status st = solve_begin<T>(P, mu, nu, phi_init, phi, w, s, true);
+    if (st != BFM_OK) return st;
+    DevState hs;
+    const int K = P->prm.check_every;
+    int it = 0;
+    while (it < P->prm.max_iters) {
+        const int cnt = P->prm.max_iters - it < K ? P->prm.max_iters - it : K;
+        HIP_TRY(enqueue_iterations<T>(P, w, mu, nu, phi, psi, it, cnt, s));
+        it += cnt;
+        HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hs.done) break;
+    }
+    HIP_TRY(enqueue_final_head<T>(P, w, mu, nu, phi, psi, it, s));
+    HIP_TRY(enqueue_finish<T>(P, w, mu, phi, psi, Tmap, s));
+    HIP_TRY(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return fill_result(hs, res);
 }
 
 extern "C" bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *phi_init, void *phi,
@@ -442,6 +501,166 @@ extern "C" bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, c
                                   (double *)phi, (double *)psi, (double *)T, w, s, result);
     return solve_impl<float>(plan, (const float *)mu, (const float *)nu, (const float *)phi_init, (float *)phi,
                              (float *)psi, (float *)T, w, s, result);
+}
+
+// ------------------------------------------------------------- batched
+
+// Many independent problems (each with its own plan, workspace and device
+// step-size state) advanced together: the first iteration is enqueued
+// directly, then `K` iterations of every problem are captured once into a
+// graph whose branches run on up to eight streams and the graph is replayed;
+// a problem whose stop flag is set turns into no-ops.  Stop flags are read
+// between replays.
+namespace {
+struct BatchStreams {
+    int nw = 0;
+    hipStream_t w[8] = {};
+    hipStream_t cap = nullptr;   // capture origin (the caller's stream may be the legacy null stream)
+    hipEvent_t fork = nullptr, join[8] = {}, capev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchStreams() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int i = 0; i < nw; ++i) {
+            if (w[i]) (void)hipStreamDestroy(w[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (capev) (void)hipEventDestroy(capev);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+    hipError_t init(int n) {
+        nw = n;
+        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&capev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        for (int i = 0; i < nw && e == hipSuccess; ++i) {
+            e = hipStreamCreateWithFlags(&w[i], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+        }
+        return e;
+    }
+    hipError_t begin(hipStream_t s) {
+        hipError_t e = hipEventRecord(fork, s);
+        for (int i = 0; i < nw && e == hipSuccess; ++i) e = hipStreamWaitEvent(w[i], fork, 0);
+        return e;
+    }
+    hipError_t end(hipStream_t s) {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < nw && e == hipSuccess; ++i) {
+            e = hipEventRecord(join[i], w[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, join[i], 0);
+        }
+        return e;
+    }
+};
+}  // namespace
+
+template <typename T>
+static bfm_status batched_impl(int np, const bfm_plan *P, const void *const *mu_, const void *const *nu_,
+                               void *const *phi_, void *const *psi_, void *const *T_, const std::vector<Ws> &w,
+                               int K, hipStream_t s, bfm_result *res)
+{
+    auto MU = [&](int p) { return (const T *)mu_[p]; };
+    auto NU = [&](int p) { return (const T *)nu_[p]; };
+    auto PHI = [&](int p) { return (T *)phi_[p]; };
+    auto PSI = [&](int p) { return (T *)psi_[p]; };
+    std::vector<DevState> hs(np);
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = solve_begin<T>(P[p], MU(p), NU(p), nullptr, PHI(p), w[p], s, false);
+        if (st != BFM_OK) return st;
+    }
+    for (int p = 0; p < np; ++p)
+        HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = check_inputs(hs[p]);
+        if (st != BFM_OK) return fail(st, "pair %d: %s", p, g_last_error.c_str());
+    }
+    BatchStreams bs;
+    HIP_TRY(bs.init(np < 8 ? np : 8));
+    auto worker = [&](int p) { return bs.w[p % bs.nw]; };
+    const int maxit = P[0]->prm.max_iters;
+    int it = 0;
+    if (maxit > 0) {
+        HIP_TRY(bs.begin(s));
+        for (int p = 0; p < np; ++p)
+            HIP_TRY(enqueue_iterations<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), 0, 1, worker(p)));
+        HIP_TRY(bs.end(s));
+        it = 1;
+    }
+    bool all_done = false;
+    if (maxit - it >= K) {
+        // capture on a private stream; the graph is then launched on `s`
+        HIP_TRY(hipStreamBeginCapture(bs.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = bs.begin(bs.cap);
+        for (int p = 0; p < np && ce == hipSuccess; ++p)
+            ce = enqueue_iterations<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), it, K, worker(p));
+        if (ce == hipSuccess) ce = bs.end(bs.cap);
+        hipError_t ee = hipStreamEndCapture(bs.cap, &bs.graph);
+        HIP_TRY(ce);
+        HIP_TRY(ee);
+        HIP_TRY(hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
+        while (maxit - it >= K) {
+            HIP_TRY(hipGraphLaunch(bs.exec, s));
+            it += K;
+            for (int p = 0; p < np; ++p)
+                HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            all_done = true;
+            for (int p = 0; p < np; ++p) all_done = all_done && hs[p].done;
+            if (all_done) break;
+        }
+    }
+    HIP_TRY(bs.begin(s));
+    for (int p = 0; p < np; ++p) {
+        if (!all_done && it < maxit)
+            HIP_TRY(enqueue_iterations<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), it, maxit - it, worker(p)));
+        HIP_TRY(enqueue_final_head<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), all_done ? it : maxit, worker(p)));
+        HIP_TRY(enqueue_finish<T>(P[p], w[p], MU(p), PHI(p), PSI(p), T_ != nullptr ? (T *)T_[p] : nullptr,
+                                  worker(p)));
+    }
+    HIP_TRY(bs.end(s));
+    for (int p = 0; p < np; ++p)
+        HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bfm_status out = BFM_OK;
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = fill_result(hs[p], res != nullptr ? &res[p] : nullptr);
+        if (st != BFM_OK && out == BFM_OK) out = st;
+    }
+    return out;
+}
+
+extern "C" bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *const *mu,
+                                        const void *const *nu, void *const *phi, void *const *psi, void *const *T,
+                                        void *const *workspaces, const size_t *ws_bytes, int32_t iters_per_graph,
+                                        void *stream, bfm_result *results)
+{
+    if (npairs < 1) return fail(BFM_EINVAL, "npairs must be >= 1");
+    if (plans == nullptr || mu == nullptr || nu == nullptr || phi == nullptr || psi == nullptr ||
+        workspaces == nullptr || ws_bytes == nullptr)
+        return fail(BFM_EINVAL, "NULL argument");
+    if (iters_per_graph < 1) return fail(BFM_EINVAL, "iters_per_graph must be >= 1");
+    std::vector<Ws> w(npairs);
+    for (int p = 0; p < npairs; ++p) {
+        if (plans[p] == nullptr) return fail(BFM_EINVAL, "plan %d is NULL", p);
+        if (plans[p]->prm.dtype != plans[0]->prm.dtype) return fail(BFM_EINVAL, "pair %d: dtype differs", p);
+        if (plans[p]->prm.max_iters != plans[0]->prm.max_iters)
+            return fail(BFM_EINVAL, "pair %d: max_iters differs (all pairs iterate together)", p);
+        if (mu[p] == nullptr || nu[p] == nullptr || phi[p] == nullptr || psi[p] == nullptr)
+            return fail(BFM_EINVAL, "pair %d: NULL field", p);
+        if (phi[p] == psi[p]) return fail(BFM_EINVAL, "pair %d: phi and psi must be distinct", p);
+        bfm_status st = check_ws(plans[p], workspaces[p], ws_bytes[p], &w[p]);
+        if (st != BFM_OK) return fail(st, "pair %d: %s", p, g_last_error.c_str());
+        for (int q = 0; q < p; ++q)
+            if (workspaces[q] == workspaces[p]) return fail(BFM_EINVAL, "pairs %d and %d share a workspace", q, p);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (plans[0]->prm.dtype == BFM_F64)
+        return batched_impl<double>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
+    return batched_impl<float>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
 }
 
 // ------------------------------------------------------------ primitives

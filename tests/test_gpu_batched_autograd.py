@@ -1,0 +1,164 @@
+"""Batched solve (one graph replay advances every problem) and the W2^2
+autograd backward (envelope gradients = mean-zeroed Kantorovich potentials,
+first variation of J, Lemma fact:derivative-J).
+
+Deposition adds with float atomics whose order varies from run to run, so two
+runs of the same problem (batched or not) agree to rounding, not bitwise."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfm as ob
+from paper_1905_12154_amd import bfm, workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def pairs(shapes, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in shapes:
+        mu = wl.random_gaussian_mixture(s, int(rng.integers(2, 5)), rng)
+        nu = wl.random_gaussian_mixture(s, int(rng.integers(2, 5)), rng)
+        out.append((mu, nu))
+    return out
+
+
+SHAPES = [(64, 64), (96, 48), (128, 128), (48, 64), (32, 24, 16), (64, 64)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("iters,K", [(20, 8), (5, 8), (0, 4), (9, 1)])
+def test_batched_equals_plain(dtype, iters, K):
+    ps = pairs(SHAPES)
+    mus = [cuda(m, dtype) for m, _ in ps]
+    nus = [cuda(n, dtype) for _, n in ps]
+    rb = bfm.solve_batched(mus, nus, max_iters=iters, iters_per_graph=K, return_map=True)
+    tol = 1e-10 if dtype == torch.float64 else 2e-5
+    for i, (m, n) in enumerate(zip(mus, nus)):
+        rp = bfm.solve(m, n, max_iters=iters, return_map=True)
+        assert rb[i].iters == rp.iters == iters
+        assert abs(rb[i].dual - rp.dual) <= tol * max(1.0, abs(rp.dual))
+        assert abs(rb[i].gap - rp.gap) <= tol * max(1e-2, rp.gap) * 10
+        assert rb[i].sigma == pytest.approx(rp.sigma, rel=1e-12)
+        for a, b in ((rb[i].phi, rp.phi), (rb[i].psi, rp.psi), (rb[i].T, rp.T)):
+            assert float((a - b).abs().max()) <= tol * max(1.0, float(b.abs().max())) * 10
+
+
+def test_batched_stop_flags_per_pair():
+    # the two discs converge early, the Gaussian pair does not: each keeps its own count
+    d_mu, d_nu = wl.two_discs(64)
+    g_mu, g_nu = pairs([(64, 64)], seed=3)[0]
+    mus, nus = [cuda(d_mu), cuda(g_mu)], [cuda(d_nu), cuda(g_nu)]
+    rb = bfm.solve_batched(mus, nus, max_iters=40, tol=2e-5, iters_per_graph=4)
+    for i in range(2):
+        rp = bfm.solve(mus[i], nus[i], max_iters=40, tol=2e-5)
+        assert (rb[i].iters, rb[i].converged) == (rp.iters, rp.converged)
+        assert abs(rb[i].dual - rp.dual) <= 1e-10
+    assert rb[0].converged and rb[0].iters < 40
+
+
+def test_batched_against_oracle():
+    ps = pairs([(48, 64), (24, 32, 16)], seed=5)
+    rb = bfm.solve_batched([cuda(m) for m, _ in ps], [cuda(n) for _, n in ps], max_iters=10)
+    for (m, n), r in zip(ps, rb):
+        o = ob.solve(m, n, ob.Params(max_iters=10))
+        assert abs(r.dual - o.dual) <= 1e-10
+        assert np.max(np.abs(host(r.phi) - o.phi)) <= 1e-7
+
+
+def test_batched_argument_errors():
+    ps = pairs([(32, 32), (32, 32)])
+    mus = [cuda(m) for m, _ in ps]
+    nus = [cuda(n) for _, n in ps]
+    shared = torch.empty(bfm.plan_for((32, 32), torch.float64).ws_bytes + 256, dtype=torch.uint8, device=DEV)
+    with pytest.raises(bfm.BFMError):
+        bfm.solve_batched(mus, nus, max_iters=3, workspaces=[shared, shared])
+
+
+# ----------------------------------------------------------------- autograd
+
+def test_grad_equals_oracle_potentials():
+    mu, nu = wl.config_c1()
+    tmu = cuda(mu).requires_grad_(True)
+    tnu = cuda(nu).requires_grad_(True)
+    loss = bfm.w2_loss(tmu, tnu, max_iters=60, tol=0.0)
+    (3.0 * loss).backward()
+    o = ob.solve(mu, nu, ob.Params(max_iters=60))
+    gmu, gnu = ob.w2_gradients(o, mu.shape)
+    assert abs(float(loss) - o.w2sq) <= 1e-5 * o.w2sq
+    assert np.max(np.abs(host(tmu.grad) - 3.0 * gmu)) <= 1e-6 * np.max(np.abs(gmu))
+    assert np.max(np.abs(host(tnu.grad) - 3.0 * gnu)) <= 1e-6 * np.max(np.abs(gnu))
+    assert abs(host(tmu.grad).sum()) <= 1e-12 * np.abs(host(tmu.grad)).sum()   # zero-mass direction
+
+
+def _fd_directions(mu, k, seed):
+    rng = np.random.default_rng(seed)
+    xs = ob.centres(mu.shape)
+    out = []
+    for _ in range(k):
+        kk = rng.integers(1, 4, size=2)
+        ph = rng.uniform(0, 2 * np.pi, size=2)
+        w = np.cos(np.pi * kk[0] * xs[0] + ph[0]) * np.cos(np.pi * kk[1] * xs[1] + ph[1])
+        v = mu * (w - (mu * w).sum() / mu.sum())
+        eps = 1e-3 / np.max(np.abs(v) / mu)
+        out.append((v, eps))
+    return out
+
+
+def test_grad_central_differences_128():
+    """Envelope gradient against central differences of the converged W2^2
+    at 128^2 along multiplicative zero-mass directions.  The discrete
+    iteration's fixed point is not the exact maximiser of the grid dual (the
+    pushforward uses the finite-difference map and multilinear deposition),
+    so the two agree to the discretisation level (the CPU oracle shows
+    0.4-1.4% here), not to rounding."""
+    mu, nu = wl.config_c5_pair(0, 128)
+    tmu = cuda(mu).requires_grad_(True)
+    loss = bfm.w2_loss(tmu, cuda(nu), max_iters=300, tol=0.0)
+    loss.backward()
+    g = host(tmu.grad)
+    errs = []
+    for v, eps in _fd_directions(mu, 4, 0):
+        wp = bfm.solve(cuda(mu + eps * v), cuda(nu), max_iters=300).w2sq
+        wm = bfm.solve(cuda(mu - eps * v), cuda(nu), max_iters=300).w2sq
+        fd = (wp - wm) / (2 * eps)
+        an = float((g * v).sum())
+        errs.append(abs(fd - an) / abs(an))
+    print("relative FD errors", errs)
+    assert max(errs) <= 3e-2
+
+
+def test_w2_loss_batched_gradients_equal_single():
+    ps = pairs([(64, 64), (96, 48), (48, 48)], seed=7)
+    mus = [cuda(m).requires_grad_(True) for m, _ in ps]
+    nus = [cuda(n).requires_grad_(True) for _, n in ps]
+    vals = bfm.w2_loss_batched(mus, nus, max_iters=30, tol=0.0)
+    (vals * torch.tensor([1.0, 2.0, -1.0], dtype=vals.dtype, device=DEV)).sum().backward()
+    for i, (m, n) in enumerate(ps):
+        a = cuda(m).requires_grad_(True)
+        b = cuda(n).requires_grad_(True)
+        l1 = bfm.w2_loss(a, b, max_iters=30, tol=0.0)
+        (l1 * [1.0, 2.0, -1.0][i]).backward()
+        assert abs(float(l1) - float(vals[i])) <= 1e-10
+        for x, y in ((a.grad, mus[i].grad), (b.grad, nus[i].grad)):
+            assert float((x - y).abs().max()) <= 1e-8 * float(y.abs().max())
+
+
+def test_grad_f32_close_to_f64():
+    mu, nu = wl.config_c5_pair(3, 128)
+    gs = []
+    for dt in (torch.float64, torch.float32):
+        t = cuda(mu, dt).requires_grad_(True)
+        bfm.w2_loss(t, cuda(nu, dt), max_iters=100, tol=0.0).backward()
+        gs.append(host(t.grad))
+    assert np.max(np.abs(gs[0] - gs[1])) <= 1e-3 * np.max(np.abs(gs[0]))
