@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--gap-iters", type=int, default=200, help="iteration cap of the time-to-gap run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched 64-pair leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 3D 384^3 leg")
+    ap.add_argument("--c5-iters", type=int, default=60)
+    ap.add_argument("--c5-tol", type=float, default=1e-4)
+    ap.add_argument("--c4-iters", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
 
@@ -64,6 +70,74 @@ def kernel_times(plan, phi, reps):
     res["ct_axis1"] = timeit(lambda: plan.ctransform_axis(f, 1, -1, out=out))
     res["ct_axis0"] = timeit(lambda: plan.ctransform_axis(a1, 0, 1, out=out))
     return res
+
+
+def batched_leg(iters, tol):
+    """64 ragged pairs (sides in {128,...,1024}, 2-6 Gaussian components):
+    plain solves one after another versus one batched solve (graph replays)
+    versus batched solve + W2^2 backward, same stop rule (gap < tol, at most
+    `iters` iterations)."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    ps = wl.config_c5()
+    mus = [torch.tensor(m, dtype=torch.float32, device=dev) for m, _ in ps]
+    nus = [torch.tensor(v, dtype=torch.float32, device=dev) for _, v in ps]
+    # warm-up: plans, workspaces, first launches
+    for m, v in zip(mus, nus):
+        bfm.solve(m, v, max_iters=1, tol=tol, return_map=False)
+    bfm.solve_batched(mus, nus, max_iters=1, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = [bfm.solve(m, v, max_iters=iters, tol=tol, return_map=False) for m, v in zip(mus, nus)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rb = bfm.solve_batched(mus, nus, max_iters=iters, tol=tol, iters_per_graph=8)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    gm = [m.clone().requires_grad_(True) for m in mus]
+    gn = [v.clone().requires_grad_(True) for v in nus]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vals = bfm.w2_loss_batched(gm, gn, max_iters=iters, tol=tol)
+    vals.sum().backward()
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    work_p = sum(m.numel() * r.iters for m, r in zip(mus, rp))
+    work_b = sum(m.numel() * r.iters for m, r in zip(mus, rb))
+    return {"pairs": len(mus), "total_points": int(sum(m.numel() for m in mus)), "tol": tol, "max_iters": iters,
+            "plain": {"seconds": tp, "pts_iters_per_s": work_p / tp, "converged": sum(r.converged for r in rp),
+                      "iters_total": sum(r.iters for r in rp)},
+            "batched": {"seconds": tb, "pts_iters_per_s": work_b / tb, "converged": sum(r.converged for r in rb),
+                        "iters_total": sum(r.iters for r in rb)},
+            "batched_plus_grad": {"seconds": tg, "pts_iters_per_s": work_b / tg},
+            "max_abs_dual_diff_batched_vs_plain": max(abs(a.dual - b.dual) for a, b in zip(rp, rb)),
+            "speedup_batched_vs_plain": tp / tb}
+
+
+def c4_leg(iters, autotune):
+    """3D 384^3, 6-Gaussian mixtures, float32: iterations per second."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c4()
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    del mu_h, nu_h
+    plan = bfm.Plan(mu.shape, torch.float32, max_iters=iters, check_every=max(iters, 1))
+    rw = plan.solve(mu, nu, return_map=False)   # warm-up (same work)
+    if autotune:
+        plan.autotune(dev, sample=rw.phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = plan.solve(mu, nu, return_map=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    N = mu.numel()
+    return {"workload": "c4: 3D 384^3, 6-Gaussian mixtures, float32", "iters": r.iters, "seconds": dt,
+            "ms_per_iter": dt / max(r.iters, 1) * 1e3, "pts_iters_per_s": N * r.iters / dt, "gap": r.gap,
+            "dual": r.dual, "tuning": plan.tuning()}
 
 
 def cpu_baseline(n):
@@ -127,6 +201,8 @@ def main():
     warm = bfm.Plan((n, n), torch.float32, max_iters=max(args.warmup, 0), check_every=max(args.warmup, 1))
     rw = warm.solve(mu, nu, return_map=False)
     plan = bfm.Plan((n, n), torch.float32, max_iters=args.steps, check_every=max(args.steps, 1))
+    # launch shapes tuned on the warm-up potential (what the timed solve sees)
+    tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = plan.solve(mu, nu, phi_init=rw.phi, return_map=False)
@@ -136,6 +212,8 @@ def main():
 
     # time to dual gap < 1e-4 from phi_0 = 0 (the trace records every head)
     gplan = bfm.Plan((n, n), torch.float32, max_iters=args.gap_iters, tol=1e-4, check_every=4)
+    if not args.no_autotune:
+        gplan.autotune(dev)   # reuses the table filled above
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     rg = gplan.solve(mu, nu, return_map=False)
@@ -175,9 +253,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
                      "kernel_ms": kt[dom], "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels_ms": kt,
+        "tuning": tuning,
         "dual": r.dual,
         "gap": r.gap,
     }
+    if not args.no_c5:
+        out["batched_c5"] = batched_leg(args.c5_iters, args.c5_tol)
+    if not args.no_c4:
+        out["c4_3d"] = c4_leg(args.c4_iters, not args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

@@ -129,6 +129,19 @@ bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *
                              void *const *phi, void *const *psi, void *const *T, void *const *workspaces,
                              const size_t *ws_bytes, int32_t iters_per_graph, void *stream, bfm_result *results);
 
+/* Autotuner: times the candidate launch shapes of the c-transform line
+ * kernel for every axis of the plan (points per lane 8 or 16; on strided
+ * axes one or four lines per workgroup), axis by axis in the order of a
+ * transform, on `sample` (a device potential of N elements, e.g. the
+ * current phi; NULL: a smooth test potential), and keeps the fastest in the
+ * plan (and in a process-wide table).  Optional: untuned plans use built-in
+ * shapes.  Synchronises `stream`; overwrites the workspace. */
+bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *workspace, size_t ws_bytes, void *stream);
+
+/* The launch shapes the plan uses: cfg6[2a] = points per lane, cfg6[2a+1] =
+ * lines per workgroup on axis a (0 = built-in choice). */
+bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg6);
+
 /* Primitive: quadratic-cost c-transform on the grid (Definition of the
  * c-transform; separable evaluation of Section 4.1; per line the Legendre
  * transform on the lower convex hull, eq. legendre / legendre_search):

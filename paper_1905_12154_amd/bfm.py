@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
                 5: "BFM_EUNSUPPORTED"}
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
-            "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched"]
+            "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
+            "bfm_plan_tuning"]
 
 
 class BFMError(RuntimeError):
@@ -75,6 +76,8 @@ def lib():
         L.bfm_poisson_neumann.argtypes = [vp, vp, vp, P(dbl), vp, sz, vp]
         L.bfm_grad.argtypes = [vp, vp, vp, dbl, vp, vp, vp, sz, vp]
         L.bfm_ctransform_axis.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.bfm_autotune.argtypes = [vp, vp, vp, sz, vp]
+        L.bfm_plan_tuning.argtypes = [vp, P(i32)]
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
                                         P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
@@ -184,6 +187,21 @@ class Plan:
         return SolveResult(phi=phi, psi=psi, T=T, dual=res.dual, primal=res.primal, gap=res.gap, G=res.G,
                            sigma=res.sigma, iters=res.iters, converged=bool(res.converged),
                            mass_mu=res.mass_mu, mass_nu=res.mass_nu)
+
+    def autotune(self, device="cuda:0", sample: Optional[torch.Tensor] = None):
+        """Time the c-transform launch shapes per axis (on ``sample``, a
+        potential of the plan's shape, when given) and keep the fastest."""
+        if sample is not None:
+            sample = self._field(sample, "sample")
+            device = sample.device
+        ws = self.workspace(device)
+        _check(lib().bfm_autotune(self._h, _ptr(sample), _ptr(ws), self.ws_bytes, _stream(torch.device(device))))
+        return self.tuning()
+
+    def tuning(self):
+        cfg = (ctypes.c_int32 * 6)()
+        _check(lib().bfm_plan_tuning(self._h, cfg))
+        return [(cfg[2 * a], cfg[2 * a + 1]) for a in range(len(self.shape))]
 
     def ctransform_axis(self, f, axis: int, sign: int = -1, out=None):
         f = self._field(f, "f")

@@ -348,15 +348,16 @@ static size_t ct_smem_for(int n, int tpl, int lpb, size_t esz)
 
 constexpr size_t kCtLdsBudget = 150 * 1024;   // gfx950: 160 KB of LDS per CU
 
-static CtShape ct_shape(int n, bool strided, size_t esz)
+static CtShape ct_shape(int n, bool strided, size_t esz, CtCfg cfg = CtCfg{})
 {
     CtShape s;
-    s.C = n > 1024 ? 16 : 8;
+    s.C = cfg.C > 0 ? cfg.C : (n > 1024 ? 16 : 8);
     const int need = (n + s.C - 1) / s.C;
     s.tpl = 1;
     while (s.tpl < need) s.tpl <<= 1;
     if (strided) {
         s.lpb = ct_smem_for(n, s.tpl, 4, esz) <= kCtLdsBudget ? 4 : 1;
+        if (cfg.lpb == 1) s.lpb = 1;
     } else {
         s.lpb = s.tpl >= 256 ? 1 : 256 / s.tpl;
         if (s.lpb > 64) s.lpb = 64;
@@ -397,9 +398,9 @@ static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long lon
 
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
-                          const int32_t *done, hipStream_t stream)
+                          const int32_t *done, hipStream_t stream, CtCfg cfg)
 {
-    const CtShape s = ct_shape(n, inner > 1, sizeof(T));
+    const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
     if (s.tpl > 256 || s.threads > 1024) return hipErrorInvalidValue;
 #define BFM_CT_CASE(CC, LL)                                                                               \
     if (s.C == CC && s.lpb == LL)                                                                         \
@@ -414,25 +415,29 @@ hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nline
 // Full c-transform of a field: out = in^c, axis ndim-1 first (u = -in), then
 // each earlier axis on the running result.
 template <typename T>
-hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream)
+hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
+                            const CtCfg *cfg)
 {
     for (int a = g.ndim - 1; a >= 0; --a) {
         const int n = g.n[a];
         const int inner = (int)g.stride[a];
         const long long nlines = g.N / n;
         hipError_t e = launch_ct_axis<T>(a == g.ndim - 1 ? in : out, out, n, inner, nlines,
-                                         a == g.ndim - 1 ? T(-1) : T(1), done, stream);
+                                         a == g.ndim - 1 ? T(-1) : T(1), done, stream,
+                                         cfg != nullptr ? cfg[a] : CtCfg{});
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 template hipError_t launch_ct_axis<float>(const float *, float *, int, int, long long, float, const int32_t *,
-                                          hipStream_t);
+                                          hipStream_t, CtCfg);
 template hipError_t launch_ct_axis<double>(const double *, double *, int, int, long long, double,
-                                           const int32_t *, hipStream_t);
-template hipError_t ctransform_field<float>(const Grid &, const float *, float *, const int32_t *, hipStream_t);
-template hipError_t ctransform_field<double>(const Grid &, const double *, double *, const int32_t *, hipStream_t);
+                                           const int32_t *, hipStream_t, CtCfg);
+template hipError_t ctransform_field<float>(const Grid &, const float *, float *, const int32_t *, hipStream_t,
+                                            const CtCfg *);
+template hipError_t ctransform_field<double>(const Grid &, const double *, double *, const int32_t *, hipStream_t,
+                                             const CtCfg *);
 template size_t ct_smem_bytes<float>(int, int, int);
 template size_t ct_smem_bytes<double>(int, int, int);
 

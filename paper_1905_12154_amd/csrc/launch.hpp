@@ -14,12 +14,19 @@ struct AxisPlan {
     int nstages;
 };
 
-// c-transform (ctransform.hip)
+// c-transform (ctransform.hip).  CtCfg overrides the launch shape of one
+// axis (0 = built-in choice): C points per lane, lines per workgroup on a
+// strided axis (1 or 4).
+struct CtCfg {
+    int C = 0;
+    int lpb = 0;
+};
 template <typename T>
-hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream);
+hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
+                            const CtCfg *cfg = nullptr);
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
-                          const int32_t *done, hipStream_t stream);
+                          const int32_t *done, hipStream_t stream, CtCfg cfg = CtCfg{});
 int ct_threads_per_line(int n);
 template <typename T> size_t ct_smem_bytes(int n, int tpl, int lpb);
 

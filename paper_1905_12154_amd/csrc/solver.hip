@@ -6,8 +6,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -52,6 +55,7 @@ struct bfm_plan_s {
     int gparts;      // partial sums of G written by the fused Poisson pass
     int nsplat;      // workgroups of the deposition kernel
     long long slot_len;
+    CtCfg ct_cfg[3];   // c-transform launch shape per axis (autotuned or built-in)
     // workspace layout (byte offsets from the workspace base)
     size_t off_state, off_trace, off_part, off_gpart, off_tables, off_pc, off_rho, off_f, total;
     size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
@@ -351,7 +355,7 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     T *pc = (T *)w.pc, *rho = (T *)w.rho, *F = (T *)w.f;
     const CtrlParams cp = ctrl_params(P);
     hipError_t e;
-    if ((e = ctransform_field<T>(g, p, pc, done, s)) != hipSuccess) return e;
+    if ((e = ctransform_field<T>(g, p, pc, done, s, P->ct_cfg)) != hipSuccess) return e;
     if (head_dot &&
         (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
@@ -364,7 +368,7 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
         return e;
     if (head_only) return hipSuccess;
     if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
-    if ((e = ctransform_field<T>(g, p, q, done, s)) != hipSuccess) return e;
+    if ((e = ctransform_field<T>(g, p, q, done, s, P->ct_cfg)) != hipSuccess) return e;
     if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
         return e;
     return launch_ctrl(w.st, w.part, w.gpart, step_mode, cp, w.trace, s);
@@ -663,6 +667,135 @@ extern "C" bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, c
     return batched_impl<float>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
 }
 
+// ------------------------------------------------------------ autotuner
+
+// Candidate c-transform launch shapes are timed per axis, in the order of a
+// transform, on a caller's sample potential (or, without one, on a smooth
+// test potential written into the workspace); the fastest is kept in the
+// plan and in a process-wide table keyed by (line length, strided, dtype,
+// lines) that later untuned requests of the same geometry reuse.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, long long>, CtCfg> g_tune;
+}
+
+template <typename T>
+__global__ void tune_field_kernel(T *f, Grid g)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        double v = 0.0;
+        for (int a = g.ndim - 1; a >= 0; --a) {
+            const double x = ((double)(r % g.n[a]) + 0.5) / g.n[a];
+            r /= g.n[a];
+            v += 0.35 * x * x - 0.1 * x + 0.01 * sin(23.0 * x + a);
+        }
+        f[i] = (T)v;
+    }
+}
+
+template <typename T>
+static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStream_t s, int reps)
+{
+    const Grid &g = P->g;
+    T *f = (T *)w.f, *o = (T *)w.pc, *nxt = (T *)w.rho;
+    if (sample != nullptr) {
+        HIP_TRY(hipMemcpyAsync(f, sample, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s));
+    } else {
+        hipLaunchKernelGGL((tune_field_kernel<T>), dim3(1024), dim3(256), 0, s, f, g);
+        HIP_TRY(hipGetLastError());
+    }
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    bfm_status out = BFM_OK;
+    // axes in the order of a transform (last axis first, its input -sample),
+    // each later axis timed on the previous pass's output
+    for (int ax = g.ndim - 1; ax >= 0 && out == BFM_OK; --ax) {
+        const int n = g.n[ax], inner = (int)g.stride[ax];
+        const long long nl = g.N / n;
+        const T sgn = ax == g.ndim - 1 ? T(-1) : T(1);
+        const auto key = std::make_tuple(n, inner > 1 ? 1 : 0, (int)sizeof(T), nl);
+        bool cached = false;
+        if (sample == nullptr) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) {
+                P->ct_cfg[ax] = it->second;
+                cached = true;
+            }
+        }
+        if (cached) {
+            HIP_TRY(launch_ct_axis<T>(f, nxt, n, inner, nl, sgn, nullptr, s, P->ct_cfg[ax]));
+            std::swap(f, nxt);
+            continue;
+        }
+        std::vector<CtCfg> cand;
+        for (int C : {8, 16})
+            for (int lpb : inner > 1 ? std::vector<int>{1, 4} : std::vector<int>{0}) {
+                if ((n + C - 1) / C > 256) continue;
+                CtCfg c;
+                c.C = C;
+                c.lpb = lpb;
+                cand.push_back(c);
+            }
+        float best = 1e30f;
+        CtCfg bestc;
+        for (const CtCfg &c : cand) {
+            hipError_t e = launch_ct_axis<T>(f, o, n, inner, nl, sgn, nullptr, s, c);   // warm-up
+            if (e != hipSuccess) continue;
+            (void)hipEventRecord(a, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_ct_axis<T>(f, o, n, inner, nl, sgn, nullptr, s, c);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess || e != hipSuccess) continue;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (ms < best) {
+                best = ms;
+                bestc = c;
+            }
+        }
+        if (best >= 1e30f) {
+            out = fail(BFM_EDEVICE, "autotune: no c-transform shape launched for axis %d", ax);
+            break;
+        }
+        P->ct_cfg[ax] = bestc;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = bestc;
+        }
+        if (launch_ct_axis<T>(f, nxt, n, inner, nl, sgn, nullptr, s, bestc) != hipSuccess) {
+            out = fail(BFM_EDEVICE, "autotune: chained pass failed on axis %d", ax);
+            break;
+        }
+        std::swap(f, nxt);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return out;
+}
+
+extern "C" bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr) return fail(BFM_EINVAL, "plan is NULL");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64) return autotune_impl<double>(plan, (const double *)sample, w, s, 5);
+    return autotune_impl<float>(plan, (const float *)sample, w, s, 5);
+}
+
+extern "C" bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg6)
+{
+    if (plan == nullptr || cfg6 == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    for (int a = 0; a < 3; ++a) {
+        cfg6[2 * a] = plan->ct_cfg[a].C;
+        cfg6[2 * a + 1] = plan->ct_cfg[a].lpb;
+    }
+    return BFM_OK;
+}
+
 // ------------------------------------------------------------ primitives
 
 extern "C" bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, void *workspace, size_t ws_bytes,
@@ -674,9 +807,9 @@ extern "C" bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, v
     if (st != BFM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (plan->prm.dtype == BFM_F64)
-        HIP_TRY(ctransform_field<double>(plan->g, (const double *)in, (double *)out, nullptr, s));
+        HIP_TRY(ctransform_field<double>(plan->g, (const double *)in, (double *)out, nullptr, s, plan->ct_cfg));
     else
-        HIP_TRY(ctransform_field<float>(plan->g, (const float *)in, (float *)out, nullptr, s));
+        HIP_TRY(ctransform_field<float>(plan->g, (const float *)in, (float *)out, nullptr, s, plan->ct_cfg));
     return BFM_OK;
 }
 
@@ -691,9 +824,10 @@ extern "C" bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t s
     const int n = g.n[axis], inner = (int)g.stride[axis];
     if (plan->prm.dtype == BFM_F64)
         HIP_TRY(launch_ct_axis<double>((const double *)in, (double *)out, n, inner, g.N / n, (double)sign, nullptr,
-                                       s));
+                                       s, plan->ct_cfg[axis]));
     else
-        HIP_TRY(launch_ct_axis<float>((const float *)in, (float *)out, n, inner, g.N / n, (float)sign, nullptr, s));
+        HIP_TRY(launch_ct_axis<float>((const float *)in, (float *)out, n, inner, g.N / n, (float)sign, nullptr, s,
+                                      plan->ct_cfg[axis]));
     return BFM_OK;
 }
 
