@@ -131,16 +131,27 @@ bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *
 
 /* Autotuner: times the candidate launch shapes of the c-transform line
  * kernel for every axis of the plan (points per lane 8 or 16; on strided
- * axes one or four lines per workgroup), axis by axis in the order of a
+ * axes one or four lines per workgroup; one line group per workgroup or
+ * persistent prefetching workgroups), axis by axis in the order of a
  * transform, on `sample` (a device potential of N elements, e.g. the
  * current phi; NULL: a smooth test potential), and keeps the fastest in the
  * plan (and in a process-wide table).  Optional: untuned plans use built-in
  * shapes.  Synchronises `stream`; overwrites the workspace. */
 bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *workspace, size_t ws_bytes, void *stream);
 
-/* The launch shapes the plan uses: cfg6[2a] = points per lane, cfg6[2a+1] =
- * lines per workgroup on axis a (0 = built-in choice). */
-bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg6);
+/* The launch shapes the plan uses, three int32 per axis a < 3:
+ * cfg9[3a] = points per lane, cfg9[3a+1] = lines per workgroup on a strided
+ * axis, cfg9[3a+2] = 1 one line group per workgroup, 2 persistent
+ * workgroups (0 everywhere = built-in choice). */
+bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg9);
+
+/* Sets the launch shapes (same layout as bfm_plan_tuning), e.g. to reuse a
+ * tuning from an earlier process.  BFM_EINVAL for values outside the listed
+ * choices or too few points per lane for the axis (C * 256 < n).  A mode-2
+ * (persistent) choice on a layout it does not apply to (n % 4 != 0 on the
+ * last axis, a strided axis with one line per workgroup or inner % 4 != 0,
+ * fields not 16-byte aligned) makes later calls fail with BFM_EDEVICE. */
+bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9);
 
 /* Primitive: quadratic-cost c-transform on the grid (Definition of the
  * c-transform; separable evaluation of Section 4.1; per line the Legendre

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
-            "bfm_plan_tuning"]
+            "bfm_plan_tuning", "bfm_plan_set_tuning"]
 
 
 class BFMError(RuntimeError):
@@ -78,6 +78,7 @@ def lib():
         L.bfm_ctransform_axis.argtypes = [vp, i32, i32, vp, vp, vp]
         L.bfm_autotune.argtypes = [vp, vp, vp, sz, vp]
         L.bfm_plan_tuning.argtypes = [vp, P(i32)]
+        L.bfm_plan_set_tuning.argtypes = [vp, P(i32)]
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
                                         P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
@@ -199,9 +200,18 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        cfg = (ctypes.c_int32 * 6)()
+        cfg = (ctypes.c_int32 * 9)()
         _check(lib().bfm_plan_tuning(self._h, cfg))
-        return [(cfg[2 * a], cfg[2 * a + 1]) for a in range(len(self.shape))]
+        return [(cfg[3 * a], cfg[3 * a + 1], cfg[3 * a + 2]) for a in range(len(self.shape))]
+
+    def set_tuning(self, cfg):
+        """Set the launch shapes: per axis (points per lane, lines per
+        workgroup, mode), as returned by ``tuning``."""
+        flat = (ctypes.c_int32 * 9)()
+        for a, tri in enumerate(cfg):
+            for k in range(3):
+                flat[3 * a + k] = int(tri[k])
+        _check(lib().bfm_plan_set_tuning(self._h, flat))
 
     def ctransform_axis(self, f, axis: int, sign: int = -1, out=None):
         f = self._field(f, "f")

@@ -63,6 +63,183 @@ template <typename T> struct vec4;
 template <> struct vec4<float> { using type = float4; };
 template <> struct vec4<double> { using type = double4; };
 
+// Wait for the lanes of one wave around LDS traffic, without a workgroup
+// barrier: a wave's LDS operations are performed in issue order, so only the
+// compiler has to be kept from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronise the lanes of one line: a line of tpl <= 64 lanes lies inside
+// one wave (lines start at multiples of tpl, a power of two).
+__device__ __forceinline__ void line_sync(int tpl) {
+    if (tpl <= kWave) wave_sync();
+    else __syncthreads();
+}
+
+// Steps 2-5 for the line of this lane, whose values are staged in v (LDS);
+// on return u holds the output at the lane's points [j0, j1).
+// Touches only this line's LDS (v, pv/nx, GH/GT) and wave_tot; all lanes of
+// the workgroup call it (its block barriers are uniform).
+template <typename T, int C>
+__device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, short *nx, int *GH, int *GT,
+                                             int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
+{
+    const T n2 = T(n) * T(n);
+    // 2. lane-local lower hull of points [j0, j1)
+    if (j0 < j1) {
+        int top = j0;
+        T utop = v[padi(j0)];
+        pv[padi(j0)] = kNone;
+        for (int j = j0 + 1; j < j1; ++j) {
+            const T uj = v[padi(j)];
+            int a = pv[padi(top)];
+            while (a >= 0) {
+                const T ua = v[padi(a)];
+                if (!above_chord(a, top, j, ua, utop, uj, n2)) break;
+                pv[padi(top)] = kDead;
+                top = a;
+                utop = ua;
+                a = pv[padi(top)];
+            }
+            pv[padi(j)] = (short)top;
+            top = j;
+            utop = uj;
+        }
+        int k = top;
+        nx[padi(k)] = kNone;
+        while (true) {
+            const int p = pv[padi(k)];
+            if (p < 0) break;
+            nx[padi(p)] = (short)k;
+            k = p;
+        }
+        GH[t] = j0;
+        GT[t] = top;
+    } else {
+        GH[t] = -1;
+        GT[t] = -1;
+    }
+
+    // 3. merge neighbouring hulls, doubling the group width each round; a
+    //    group of 2r <= 64 lanes lies in one wave and synchronises only it
+    for (int r = 1; r < tpl; r <<= 1) {
+        if (2 * r <= kWave) wave_sync();
+        else __syncthreads();
+        if ((t & (2 * r - 1)) == 0 && t + r < tpl) {
+            const int hL = GH[t], tL = GT[t], hR = GH[t + r], tR = GT[t + r];
+            if (hR >= 0) {
+                if (hL < 0) {
+                    GH[t] = hR;
+                    GT[t] = tR;
+                } else {
+                    int a = tL, b = hR;
+                    T ua = v[padi(a)], ub = v[padi(b)];
+                    for (;;) {
+                        bool moved = false;
+                        const int pa = pv[padi(a)];
+                        if (pa >= 0) {
+                            const T upa = v[padi(pa)];
+                            if (above_chord(pa, a, b, upa, ua, ub, n2)) {
+                                pv[padi(a)] = kDead;
+                                a = pa;
+                                ua = upa;
+                                moved = true;
+                            }
+                        }
+                        const int nb = nx[padi(b)];
+                        if (nb >= 0) {
+                            const T unb = v[padi(nb)];
+                            if (above_chord(a, b, nb, ua, ub, unb, n2)) {
+                                pv[padi(b)] = kDead;
+                                b = nb;
+                                ub = unb;
+                                moved = true;
+                            }
+                        }
+                        if (!moved) break;
+                    }
+                    nx[padi(a)] = (short)b;
+                    pv[padi(b)] = (short)a;
+                    GT[t] = tR;
+                }
+            }
+        }
+    }
+    line_sync(tpl);
+
+    // 4. start index of every surviving vertex (registers), then markers
+    int st[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = j0 + c;
+        st[c] = n;
+        if (j < j1) {
+            const int p = pv[padi(j)];
+            if (p == kNone) {
+                st[c] = 0;
+            } else if (p >= 0) {
+                T s = T(0.5) * T(j + p) + n2 * (v[padi(j)] - v[padi(p)]) / T(j - p);
+                s = fmin(fmax(s, T(-1)), T(n));
+                const int si = (int)ceil(s);
+                st[c] = si < 0 ? 0 : si;
+            }
+        }
+    }
+    line_sync(tpl);
+    int *mk = reinterpret_cast<int *>(pv);   // NP ints over this line's prev/next links
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c < j1) mk[padi(j0 + c)] = -1;
+    line_sync(tpl);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (st[c] < n) atomicMax(&mk[padi(st[c])], j0 + c);
+    line_sync(tpl);
+
+    // prefix maximum of the markers along the line
+    int loc[C];
+    int m = -1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (j0 + c < j1) m = max(m, mk[padi(j0 + c)]);
+        loc[c] = m;
+    }
+    // inclusive scan over the lanes of this line: shuffles inside a wave
+    // (segments of tpl lanes when tpl < 64), wave totals through LDS
+    const int seg = tpl < kWave ? tpl : kWave;
+    int incl = m;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int o = __shfl_up(incl, off, seg);
+        if (off < seg && (t % seg) >= off) incl = max(incl, o);
+    }
+    int excl = __shfl_up(incl, 1, seg);
+    if (t % seg == 0) excl = -1;
+    if (tpl > kWave) {
+        const int tid = threadIdx.x;
+        const int w = tid / kWave;
+        if ((tid & (kWave - 1)) == kWave - 1) wave_tot[w] = incl;
+        __syncthreads();
+        const int wl0 = (l * tpl) / kWave;   // first wave of this line
+        for (int q = wl0; q < w; ++q) excl = max(excl, wave_tot[q]);
+    }
+
+    // 5. evaluate at the selected vertex
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j = j0 + c;
+        if (j < j1) {
+            const int k = max(excl, loc[c]);
+            const T d = T(j - k) * h;
+            u[c] = T(0.5) * d * d + v[padi(k)];
+        }
+    }
+}
+
+// One group of LPB lines per workgroup: any line length, stride or alignment.
 template <typename T, int C, int LPB>
 __global__ void __launch_bounds__(1024)
 ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
@@ -84,9 +261,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
     const int j0 = t * C, j1 = min(j0 + C, n);
     T *v = vals + l * NP;
     short *pv = links + (size_t)l * 2 * NP;
-    short *nx = pv + NP;
     int *GH = grp + l * 2 * tpl;
-    int *GT = GH + tpl;
 
     T u[C];
     // 1. stage the lines (u = sgn * in)
@@ -135,159 +310,11 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
                 vals[ll * NP + padi(j)] = LL < nlines ? sgn * in[line_base(LL, n, inner) + (long long)j * inner] : T(0);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
     }
-    __syncthreads();
+    if (inner == 1) line_sync(tpl);   // rows: every lane staged only its own line
+    else __syncthreads();
 
-    const T n2 = T(n) * T(n);
-    // 2. lane-local lower hull of points [j0, j1)
-    if (j0 < j1) {
-        int top = j0;
-        T utop = u[0];
-        pv[padi(j0)] = kNone;
-        for (int j = j0 + 1; j < j1; ++j) {
-            const T uj = v[padi(j)];
-            int a = pv[padi(top)];
-            while (a >= 0) {
-                const T ua = v[padi(a)];
-                if (!above_chord(a, top, j, ua, utop, uj, n2)) break;
-                pv[padi(top)] = kDead;
-                top = a;
-                utop = ua;
-                a = pv[padi(top)];
-            }
-            pv[padi(j)] = (short)top;
-            top = j;
-            utop = uj;
-        }
-        int k = top;
-        nx[padi(k)] = kNone;
-        while (true) {
-            const int p = pv[padi(k)];
-            if (p < 0) break;
-            nx[padi(p)] = (short)k;
-            k = p;
-        }
-        GH[t] = j0;
-        GT[t] = top;
-    } else {
-        GH[t] = -1;
-        GT[t] = -1;
-    }
-    __syncthreads();
-
-    // 3. merge neighbouring hulls, doubling the group width each round
-    for (int r = 1; r < tpl; r <<= 1) {
-        if ((t & (2 * r - 1)) == 0 && t + r < tpl) {
-            const int hL = GH[t], tL = GT[t], hR = GH[t + r], tR = GT[t + r];
-            if (hR >= 0) {
-                if (hL < 0) {
-                    GH[t] = hR;
-                    GT[t] = tR;
-                } else {
-                    int a = tL, b = hR;
-                    T ua = v[padi(a)], ub = v[padi(b)];
-                    for (;;) {
-                        bool moved = false;
-                        const int pa = pv[padi(a)];
-                        if (pa >= 0) {
-                            const T upa = v[padi(pa)];
-                            if (above_chord(pa, a, b, upa, ua, ub, n2)) {
-                                pv[padi(a)] = kDead;
-                                a = pa;
-                                ua = upa;
-                                moved = true;
-                            }
-                        }
-                        const int nb = nx[padi(b)];
-                        if (nb >= 0) {
-                            const T unb = v[padi(nb)];
-                            if (above_chord(a, b, nb, ua, ub, unb, n2)) {
-                                pv[padi(b)] = kDead;
-                                b = nb;
-                                ub = unb;
-                                moved = true;
-                            }
-                        }
-                        if (!moved) break;
-                    }
-                    nx[padi(a)] = (short)b;
-                    pv[padi(b)] = (short)a;
-                    GT[t] = tR;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    // 4. start index of every surviving vertex (registers), then markers
-    int st[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int j = j0 + c;
-        st[c] = n;
-        if (j < j1) {
-            const int p = pv[padi(j)];
-            if (p == kNone) {
-                st[c] = 0;
-            } else if (p >= 0) {
-                T s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) / T(j - p);
-                s = fmin(fmax(s, T(-1)), T(n));
-                const int si = (int)ceil(s);
-                st[c] = si < 0 ? 0 : si;
-            }
-        }
-    }
-    __syncthreads();
-    int *mk = reinterpret_cast<int *>(pv);   // NP ints over this line's prev/next links
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        if (j0 + c < j1) mk[padi(j0 + c)] = -1;
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-        if (st[c] < n) atomicMax(&mk[padi(st[c])], j0 + c);
-    __syncthreads();
-
-    // prefix maximum of the markers along the line
-    int loc[C];
-    int m = -1;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        if (j0 + c < j1) m = max(m, mk[padi(j0 + c)]);
-        loc[c] = m;
-    }
-    // inclusive scan over the lanes of this line: shuffles inside a wave
-    // (segments of tpl lanes when tpl < 64), wave totals through LDS
-    const int seg = tpl < kWave ? tpl : kWave;
-    int incl = m;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int o = __shfl_up(incl, off, seg);
-        if (off < seg && (t % seg) >= off) incl = max(incl, o);
-    }
-    int excl = __shfl_up(incl, 1, seg);
-    if (t % seg == 0) excl = -1;
-    if (tpl > kWave) {
-        const int w = tid / kWave;
-        if ((tid & (kWave - 1)) == kWave - 1) wave_tot[w] = incl;
-        __syncthreads();
-        const int wl0 = (l * tpl) / kWave;   // first wave of this line
-        for (int q = wl0; q < w; ++q) excl = max(excl, wave_tot[q]);
-    }
-
-    // 5. evaluate at the selected vertex
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int j = j0 + c;
-        if (j < j1) {
-            const int k = max(excl, loc[c]);
-            const T d = T(j - k) * h;
-            u[c] = T(0.5) * d * d + v[padi(k)];
-        }
-    }
+    ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
 
     if (inner == 1) {
         const bool vec = (n & 3) == 0 && (C & 3) == 0 && out_al;
@@ -327,6 +354,126 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
                 const long long LL = L0 + ll;
                 if (LL < nlines) out[line_base(LL, n, inner) + (long long)j * inner] = vals[ll * NP + padi(j)];
             }
+        }
+    }
+}
+
+// Persistent workgroups with prefetch, for the aligned cases: contiguous
+// lines with n % 4 == 0 (STRIDED = false), or four adjacent strided lines per
+// group with inner % 4 == 0 (STRIDED = true, LPB = 4); both with 16-byte
+// aligned fields.  Workgroup b takes the groups xcd_block(b) + k * gridDim;
+// the C values each lane needs for the next group (tpl * C >= n, so a lane's
+// share of LPB * n values is at most C) are loaded into registers while the
+// current group is transformed from LDS.
+template <typename T, int C, int LPB, bool STRIDED>
+__global__ void __launch_bounds__(1024)
+ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
+                   T sgn, T h, const int32_t *__restrict__ done)
+{
+    static_assert(C % 4 == 0 && (!STRIDED || LPB == 4), "vector layout");
+    if (done != nullptr && *done) return;
+    using V4 = typename vec4<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int NP = padded_len(n);
+    T *vals = reinterpret_cast<T *>(smem);
+    short *links = reinterpret_cast<short *>(vals + (size_t)LPB * NP);
+    int *grp = reinterpret_cast<int *>(links + (size_t)LPB * 2 * NP);
+    __shared__ int wave_tot[16];
+
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int l = tid / tpl, t = tid - l * tpl;
+    const int jb = t * C;
+    T *v = vals + l * NP;
+    short *pv = links + (size_t)l * 2 * NP;
+    int *GH = grp + l * 2 * tpl;
+    const long long step = (long long)gridDim.x * LPB;
+
+    V4 pf[C / 4] = {};
+    auto fetch = [&](long long G0) {
+        if (!STRIDED) {
+            const long long L = G0 + l;
+            const V4 *src = reinterpret_cast<const V4 *>(in + L * n + jb);
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q)
+                if (L < nlines && jb + 4 * q < n) pf[q] = src[q];
+        } else {
+            const T *src = in + line_base(G0, n, inner);
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                const int j = tid + q * nthr;
+                if (j < n) pf[q] = *reinterpret_cast<const V4 *>(src + (long long)j * inner);
+            }
+        }
+    };
+
+    long long G0 = xcd_block(blockIdx.x, gridDim.x) * LPB;
+    if (G0 < nlines) fetch(G0);
+    for (; G0 < nlines; G0 += step) {
+        // the lane's first point, re-derived every pass so that the compiler
+        // does not keep C precomputed LDS addresses per array over the loop
+        int j0 = jb;
+        __asm__ volatile("" : "+v"(j0));
+        const int j1 = min(j0 + C, n);
+        const long long L = G0 + l;
+        T u[C];
+        if (!STRIDED) {
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                u[4 * q] = sgn * pf[q].x;
+                u[4 * q + 1] = sgn * pf[q].y;
+                u[4 * q + 2] = sgn * pf[q].z;
+                u[4 * q + 3] = sgn * pf[q].w;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            line_sync(tpl);
+        } else {
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                const int j = tid + q * nthr;
+                if (j < n) {
+                    const int pj = padi(j);
+                    vals[0 * NP + pj] = sgn * pf[q].x;
+                    vals[1 * NP + pj] = sgn * pf[q].y;
+                    vals[2 * NP + pj] = sgn * pf[q].z;
+                    vals[3 * NP + pj] = sgn * pf[q].w;
+                }
+            }
+            __syncthreads();
+        }
+        if (G0 + step < nlines) fetch(G0 + step);   // in flight during the transform
+
+        ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
+
+        if (!STRIDED) {
+            if (L < nlines && j0 < j1) {
+                V4 *dst = reinterpret_cast<V4 *>(out + L * n + j0);
+#pragma unroll
+                for (int q = 0; q < C / 4; ++q) {
+                    if (j0 + 4 * q < n) {
+                        V4 x;
+                        x.x = u[4 * q]; x.y = u[4 * q + 1]; x.z = u[4 * q + 2]; x.w = u[4 * q + 3];
+                        dst[q] = x;
+                    }
+                }
+            }
+            line_sync(tpl);   // the next group restages this line's LDS
+        } else {
+            line_sync(tpl);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            __syncthreads();
+            T *dst = out + line_base(G0, n, inner);
+            for (int j = tid; j < n; j += nthr) {
+                const int pj = padi(j);
+                V4 x;
+                x.x = vals[0 * NP + pj]; x.y = vals[1 * NP + pj]; x.z = vals[2 * NP + pj]; x.w = vals[3 * NP + pj];
+                *reinterpret_cast<V4 *>(dst + (long long)j * inner) = x;
+            }
+            __syncthreads();
         }
     }
 }
@@ -375,25 +522,82 @@ int ct_threads_per_line(int n) { return ct_shape(n, false, 4).tpl; }
 template <typename T>
 size_t ct_smem_bytes(int n, int tpl, int lpb) { return ct_smem_for(n, tpl, lpb, sizeof(T)); }
 
+// Workgroups resident at once for a kernel (the persistent grid size).
+static long long resident_blocks(const void *fn, int threads, size_t smem)
+{
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, smem) != hipSuccess || occ < 1) occ = 1;
+    return (long long)occ * ncu;
+}
+
+template <typename KernelT>
+static hipError_t allow_smem(KernelT fn, size_t smem, bool &done_flag)
+{
+    if (smem > 64 * 1024 && !done_flag) {
+        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        done_flag = true;
+    }
+    return hipSuccess;
+}
+
 template <typename T, int C, int LPB>
 static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads,
-                                 T sgn, const int32_t *done, hipStream_t stream)
+                                 T sgn, const int32_t *done, hipStream_t stream, bool persistent)
 {
     const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
-    const long long blocks = (nlines + LPB - 1) / LPB;
+    const long long groups = (nlines + LPB - 1) / LPB;
     const T h = T(1.0) / T(n);
-    if (smem > 64 * 1024) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)ct_lines_kernel<T, C, LPB>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-            if (e != hipSuccess) return e;
-            attr_set = true;
+    if (persistent) {
+        if constexpr (LPB == 4) {
+            if (inner > 1) {
+                static bool attr = false;
+                auto fn = ct_lines_pf_kernel<T, C, 4, true>;
+                hipError_t e = allow_smem(fn, smem, attr);
+                if (e != hipSuccess) return e;
+                long long blocks = resident_blocks((const void *)fn, threads, smem);
+                if (blocks > groups) blocks = groups;
+                hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner,
+                                   nlines, tpl, sgn, h, done);
+                return hipGetLastError();
+            }
         }
+        if (inner == 1) {
+            static bool attr = false;
+            auto fn = ct_lines_pf_kernel<T, C, LPB, false>;
+            hipError_t e = allow_smem(fn, smem, attr);
+            if (e != hipSuccess) return e;
+            long long blocks = resident_blocks((const void *)fn, threads, smem);
+            if (blocks > groups) blocks = groups;
+            hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner, nlines,
+                               tpl, sgn, h, done);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((ct_lines_kernel<T, C, LPB>), dim3((unsigned)blocks), dim3(threads), smem, stream, in,
+    static bool attr = false;
+    hipError_t e = allow_smem(ct_lines_kernel<T, C, LPB>, smem, attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ct_lines_kernel<T, C, LPB>), dim3((unsigned)groups), dim3(threads), smem, stream, in,
                        out, n, inner, nlines, tpl, sgn, h, done);
     return hipGetLastError();
+}
+
+// The persistent kernel applies where its vector layout does: contiguous
+// lines of n % 4 == 0, or four strided lines per group with inner % 4 == 0,
+// with 16-byte aligned fields.
+static bool ct_persistent_ok(int n, int inner, int lpb, const void *in, const void *out)
+{
+    if ((((uintptr_t)in | (uintptr_t)out) & 15) != 0) return false;
+    if (inner == 1) return (n & 3) == 0;
+    return lpb == 4 && (inner & 3) == 0;
 }
 
 template <typename T>
@@ -402,9 +606,12 @@ hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nline
 {
     const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
     if (s.tpl > 256 || s.threads > 1024) return hipErrorInvalidValue;
+    const bool ok = ct_persistent_ok(n, inner, s.lpb, in, out);
+    if (cfg.pers == 2 && !ok) return hipErrorInvalidValue;
+    const bool pers = ok && (cfg.pers == 2 || (cfg.pers == 0 && sizeof(T) == 4));
 #define BFM_CT_CASE(CC, LL)                                                                               \
     if (s.C == CC && s.lpb == LL)                                                                         \
-        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream);
+        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream, pers);
     BFM_CT_CASE(16, 1) BFM_CT_CASE(16, 4) BFM_CT_CASE(8, 1) BFM_CT_CASE(8, 2) BFM_CT_CASE(8, 4)
     BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
     BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64)

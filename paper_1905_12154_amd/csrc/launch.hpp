@@ -16,10 +16,12 @@ struct AxisPlan {
 
 // c-transform (ctransform.hip).  CtCfg overrides the launch shape of one
 // axis (0 = built-in choice): C points per lane, lines per workgroup on a
-// strided axis (1 or 4).
+// strided axis (1 or 4), pers = 1 one line group per workgroup, 2 persistent
+// workgroups with prefetch (aligned layouts only).
 struct CtCfg {
     int C = 0;
     int lpb = 0;
+    int pers = 0;
 };
 template <typename T>
 hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,

@@ -732,13 +732,15 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
         }
         std::vector<CtCfg> cand;
         for (int C : {8, 16})
-            for (int lpb : inner > 1 ? std::vector<int>{1, 4} : std::vector<int>{0}) {
-                if ((n + C - 1) / C > 256) continue;
-                CtCfg c;
-                c.C = C;
-                c.lpb = lpb;
-                cand.push_back(c);
-            }
+            for (int lpb : inner > 1 ? std::vector<int>{1, 4} : std::vector<int>{0})
+                for (int pers : {1, 2}) {
+                    if ((n + C - 1) / C > 256) continue;
+                    CtCfg c;
+                    c.C = C;
+                    c.lpb = lpb;
+                    c.pers = pers;
+                    cand.push_back(c);   // shapes that do not apply fail to launch and are skipped
+                }
         float best = 1e30f;
         CtCfg bestc;
         for (const CtCfg &c : cand) {
@@ -786,12 +788,32 @@ extern "C" bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *work
     return autotune_impl<float>(plan, (const float *)sample, w, s, 5);
 }
 
-extern "C" bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg6)
+extern "C" bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9)
 {
-    if (plan == nullptr || cfg6 == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    if (plan == nullptr || cfg9 == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    CtCfg c[3];
     for (int a = 0; a < 3; ++a) {
-        cfg6[2 * a] = plan->ct_cfg[a].C;
-        cfg6[2 * a + 1] = plan->ct_cfg[a].lpb;
+        const int C = cfg9[3 * a], lpb = cfg9[3 * a + 1], pers = cfg9[3 * a + 2];
+        if ((C != 0 && C != 8 && C != 16) || (lpb != 0 && lpb != 1 && lpb != 4) || pers < 0 || pers > 2)
+            return fail(BFM_EINVAL, "tuning of axis %d: points per lane %d (0, 8, 16), lines %d (0, 1, 4), mode %d (0-2)",
+                        a, C, lpb, pers);
+        if (a < plan->g.ndim && C != 0 && (plan->g.n[a] + C - 1) / C > 256)
+            return fail(BFM_EINVAL, "tuning of axis %d: %d points per lane do not cover %d points", a, C, plan->g.n[a]);
+        c[a].C = C;
+        c[a].lpb = lpb;
+        c[a].pers = pers;
+    }
+    for (int a = 0; a < 3; ++a) plan->ct_cfg[a] = c[a];
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg9)
+{
+    if (plan == nullptr || cfg9 == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    for (int a = 0; a < 3; ++a) {
+        cfg9[3 * a] = plan->ct_cfg[a].C;
+        cfg9[3 * a + 1] = plan->ct_cfg[a].lpb;
+        cfg9[3 * a + 2] = plan->ct_cfg[a].pers;
     }
     return BFM_OK;
 }

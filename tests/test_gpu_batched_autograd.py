@@ -95,7 +95,7 @@ def test_grad_equals_oracle_potentials():
     (3.0 * loss).backward()
     o = ob.solve(mu, nu, ob.Params(max_iters=60))
     gmu, gnu = ob.w2_gradients(o, mu.shape)
-    assert abs(float(loss) - o.w2sq) <= 1e-5 * o.w2sq
+    assert abs(float(loss.detach()) - o.w2sq) <= 1e-5 * o.w2sq
     assert np.max(np.abs(host(tmu.grad) - 3.0 * gmu)) <= 1e-6 * np.max(np.abs(gmu))
     assert np.max(np.abs(host(tnu.grad) - 3.0 * gnu)) <= 1e-6 * np.max(np.abs(gnu))
     assert abs(host(tmu.grad).sum()) <= 1e-12 * np.abs(host(tmu.grad)).sum()   # zero-mass direction

@@ -69,6 +69,67 @@ def test_ctransform_f32(shape, kind):
     assert np.max(np.abs(got - ref)) <= 300 * np.finfo(np.float32).eps * scale
 
 
+def _ct_modes(shape, esz):
+    """Every launch mode that applies to a shape: points per lane, lines per
+    workgroup on strided axes, one group per workgroup (1) or persistent (2)."""
+    def four_lines_fit(n, C, esz):   # LDS of a four-line group within the 150 KB budget
+        tpl = 1 << int(np.ceil(np.log2(max(1, -(-n // C)))))
+        npad = n + n // 16 + 1
+        return ((4 * npad * esz + 8 * npad * 2 + 3) & ~3) + 32 * tpl <= 150 * 1024
+
+    out = []
+    for C in (8, 16):
+        if any(C * 256 < n for n in shape):
+            continue
+        for lpb in (1, 4):
+            for pers in (1, 2):
+                # persistent: rows need n % 4 == 0; a strided axis needs a group of
+                # four lines (inner % 4 == 0, LDS room, >= 16 lanes per line)
+                ok = shape[-1] % 4 == 0 and all(
+                    lpb == 4 and int(np.prod(shape[a + 1:])) % 4 == 0 and four_lines_fit(shape[a], C, esz)
+                    and -(-shape[a] // C) > 8 for a in range(len(shape) - 1))
+                # True: must run; False: must be rejected; None: either (the
+                # launch shape may widen a group to whole waves)
+                out.append(((C, lpb, pers), True if pers == 1 or ok else (False if shape[-1] % 4 else None)))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (96, 48), (6, 12), (24, 36), (16, 54), (384, 128), (1024, 8),
+                                   (24, 32, 18), (8, 12, 24), (4096, 16)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ctransform_every_launch_mode(shape, dtype):
+    """Each c-transform kernel variant (including the persistent prefetching
+    one, with its wave-level merge synchronisation) against the definition."""
+    f = rand_field(shape, 3, "potential")
+    if dtype == torch.float32:
+        f = f.astype(np.float32).astype(np.float64)
+    ref = ob.ctransform(f)
+    tol = (1e-13 if dtype == torch.float64 else 300 * np.finfo(np.float32).eps) * max(1.0, np.max(np.abs(ref)))
+    plan = bfm.Plan(shape, dtype)
+    for mode, applies in _ct_modes(shape, 8 if dtype == torch.float64 else 4):
+        plan.set_tuning([mode] * len(shape))
+        assert plan.tuning() == [mode] * len(shape)
+        if applies is False:
+            with pytest.raises(bfm.BFMError):
+                plan.ctransform(cuda(f, dtype))
+            continue
+        try:
+            got = host(plan.ctransform(cuda(f, dtype)))
+        except bfm.BFMError:
+            assert applies is None, mode
+            continue
+        assert np.max(np.abs(got - ref)) <= tol, mode
+
+
+def test_set_tuning_rejects_bad_values():
+    plan = bfm.Plan((64, 4096), torch.float32)
+    for bad in ([(12, 0, 0), (0, 0, 0)], [(8, 2, 0), (0, 0, 0)], [(8, 4, 3), (0, 0, 0)], [(0, 0, 0), (8, 0, 0)]):
+        with pytest.raises(bfm.BFMError) as e:
+            plan.set_tuning(bad)
+        assert e.value.status == bfm.BFM_EINVAL
+    assert plan.tuning() == [(0, 0, 0), (0, 0, 0)]
+
+
 def test_ctransform_in_place_and_linear_closed_form():
     shape = (96, 128)
     xs = ob.centres(shape)
