@@ -25,6 +25,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-pts×iters/s & time to dual gap<1e-4 at 4096²; batched+grad vs plain"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20     # calibration copy: reads and writes this many bytes
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ct_axis0_c3_4096_f32_traffic.json")
+# sources that decide the c-transform kernel's code: counters taken on
+# another version of them no longer describe the kernel
+TRAFFIC_SOURCES = ["paper_1905_12154_amd/csrc/ctransform.hip", "paper_1905_12154_amd/csrc/common.hpp",
+                   "paper_1905_12154_amd/csrc/launch.hpp", "paper_1905_12154_amd/build_lib.py"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, tuning_axis):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by the counter's reading on
+    a copy of known size), or None when the kernel's sources or launch shape
+    differ from those the counters were taken on."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256") != kernel_source_hash():
+        return None
+    if tuning_axis is not None and list(t.get("launch_shape", [])) != list(tuning_axis):
+        return None
+    return t["hbm_bytes_per_launch"]
 
 
 def parse():
@@ -42,6 +74,9 @@ def parse():
     ap.add_argument("--c5-tol", type=float, default=1e-4)
     ap.add_argument("--c4-iters", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--pmc-leg", action="store_true",
+                    help="only the dominant kernel's timing leg plus a %d MiB copy for counter calibration "
+                         "(the program run under rocprofv3 --pmc)" % (COPY_BYTES >> 20))
     return ap.parse_args()
 
 
@@ -181,6 +216,30 @@ def cpu_baseline(n):
             "seconds_per_iter": t_iter}
 
 
+def pmc_leg(n, args):
+    """What the counter runs profile: the c3 warm-up potential, the tuned
+    launch shapes, `kernel_reps` launches of each c-transform pass, then one
+    device copy of COPY_BYTES (the calibration kernel)."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c3(n)
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    warm = bfm.Plan((n, n), torch.float32, max_iters=max(args.warmup, 0), check_every=max(args.warmup, 1))
+    rw = warm.solve(mu, nu, return_map=False)
+    plan = bfm.Plan((n, n), torch.float32)
+    tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
+    kt = kernel_times(plan, rw.phi, args.kernel_reps)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_leg": True, "tuning": tuning, "kernels_ms": kt, "kernel_reps": args.kernel_reps,
+                      "copy_bytes": COPY_BYTES, "source_sha256": kernel_source_hash()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -193,6 +252,9 @@ def main():
 
     dev = torch.device("cuda:0")
     n = args.n
+    if args.pmc_leg:
+        pmc_leg(n, args)
+        return
     mu_h, nu_h = wl.config_c3(n)
     mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
     nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
@@ -228,6 +290,7 @@ def main():
     dom = max(per_iter, key=per_iter.get)
     bytes_per_launch = 2 * N * 4          # read u, write the transformed line (float32)
     achieved = bytes_per_launch / (kt[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, tuning[0 if dom == "ct_axis0" else 1] if tuning else None)
 
     out = {
         "metric": METRIC,
@@ -250,7 +313,7 @@ def main():
                              "converged": bool(rg.converged), "final_gap": rg.gap, "min_gap": min_gap,
                              "dual": rg.dual, "cap": args.gap_iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "kernel_ms": kt[dom], "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernels_ms": kt,
         "tuning": tuning,
