@@ -15,8 +15,9 @@
 // Each line is reordered (even samples forward, odd samples backward) so the
 // DCT becomes one length-n complex DFT plus a quarter-wave twiddle (Makhoul's
 // method); two real lines share one complex DFT (real and imaginary parts).
-// The DFT is a Stockham auto-sort FFT in LDS with radix 4, 2 and 3 stages
-// (n = 2^a 3^b), twiddles from a per-axis table.
+// The DFT is a Stockham auto-sort FFT in LDS with radix 16, 8, 4, 2 and 3
+// stages (n = 2^a 3^b; radix-16 and radix-8 butterflies are done in
+// registers), twiddles from a per-axis table.
 //
 // Passes (2D): forward along rows (input tgt - rho, rho cleared for the next
 // deposition) -> along columns forward, divide by lambda, inverse (one
@@ -41,9 +42,74 @@ __device__ __forceinline__ long long xcd_map(long long b, long long nb) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// exp(-2 pi i e / 16) for 0 <= e < 16, exact to the type's rounding
+template <typename T>
+__device__ __forceinline__ cpx<T> w16(int e) {
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, r2 = 0.70710678118654752440;
+    constexpr double cs[16] = {1, c1, r2, s1, 0, -s1, -r2, -c1, -1, -c1, -r2, -s1, 0, s1, r2, c1};
+    constexpr double sn[16] = {0, s1, r2, c1, 1, c1, r2, s1, 0, -s1, -r2, -c1, -1, -c1, -r2, -s1};
+    return {T(cs[e & 15]), T(-sn[e & 15])};
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4_inplace(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> &x3) {
+    const cpx<T> a = cadd(x0, x2), b = csub(x0, x2);
+    const cpx<T> c = cadd(x1, x3), d = csub(x1, x3);
+    const cpx<T> dmi = {d.y, -d.x};   // -i d
+    x0 = cadd(a, c);
+    x1 = cadd(b, dmi);
+    x2 = csub(a, c);
+    x3 = csub(b, dmi);
+}
+
+// Products by the constant twiddles of the register radix-8/16 transforms:
+// multiplications by -i and exp(-i pi/4)-type factors are spelled out.
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_w16(cpx<T> x, int e) {
+    if (e == 0) return x;
+    if (e == 4) return {x.y, -x.x};
+    return cmul(x, w16<T>(e));
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void small_dft(cpx<T> *x) {
-    if constexpr (R == 2) {
+    if constexpr (R == 16) {
+        // decimation in frequency, 16 = 4 x 4: row DFTs over s of x[j + 4 s],
+        // twiddles w16^(j r), column DFTs over j; output X[4 m + r]
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            dft4_inplace(x[j], x[j + 4], x[j + 8], x[j + 12]);
+#pragma unroll
+            for (int r = 1; r < 4; ++r) x[j + 4 * r] = mul_w16(x[j + 4 * r], j * r);
+        }
+        cpx<T> y[16];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            cpx<T> u0 = x[4 * r], u1 = x[4 * r + 1], u2 = x[4 * r + 2], u3 = x[4 * r + 3];
+            dft4_inplace(u0, u1, u2, u3);
+            y[r] = u0;
+            y[4 + r] = u1;
+            y[8 + r] = u2;
+            y[12 + r] = u3;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = y[k];
+    } else if constexpr (R == 8) {
+        // decimation in frequency, 8 = 2 x 4
+        cpx<T> a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = cadd(x[j], x[j + 4]);
+            b[j] = mul_w16(csub(x[j], x[j + 4]), 2 * j);
+        }
+        dft4_inplace(a[0], a[1], a[2], a[3]);
+        dft4_inplace(b[0], b[1], b[2], b[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            x[2 * m] = a[m];
+            x[2 * m + 1] = b[m];
+        }
+    } else if constexpr (R == 2) {
         const cpx<T> a = x[0], b = x[1];
         x[0] = cadd(a, b);
         x[1] = csub(a, b);
@@ -105,13 +171,24 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
     __syncthreads();
 }
 
-// Stage counts are packed as radices = n4 | n2 << 8 | n3 << 16 (radix-4
-// stages first, then radix 2, then radix 3); one loop per radix keeps each
-// stage's register footprint separate.
+// Stage counts are packed as radices = n16 | n8 << 6 | n4 << 12 | n2 << 18 |
+// n3 << 24 (stages in that order); one loop per radix keeps each stage's
+// register footprint separate.
 template <typename T, int VMAX>
 __device__ void fft_lds(cpx<T> *buf, int n, uint32_t radices, int lt, int bd, const cpx<T> *__restrict__ tw) {
-    const int n4 = radices & 0xff, n2 = (radices >> 8) & 0xff, n3 = (radices >> 16) & 0xff;
+    const int n16 = radices & 63, n8 = (radices >> 6) & 63, n4 = (radices >> 12) & 63;
+    const int n2 = (radices >> 18) & 63, n3 = (radices >> 24) & 63;
     int p = 1;
+#pragma unroll 1
+    for (int s = 0; s < n16; ++s) {
+        fft_stage<T, VMAX, 16>(buf, n, p, lt, bd, tw);
+        p *= 16;
+    }
+#pragma unroll 1
+    for (int s = 0; s < n8; ++s) {
+        fft_stage<T, VMAX, 8>(buf, n, p, lt, bd, tw);
+        p *= 8;
+    }
 #pragma unroll 1
     for (int s = 0; s < n4; ++s) {
         fft_stage<T, VMAX, 4>(buf, n, p, lt, bd, tw);

@@ -72,16 +72,19 @@ static bool is_2a3b(int n)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// FFT stage counts: n = 4^n4 2^n2 3^n3, packed as n4 | n2 << 8 | n3 << 16.
+// FFT stage counts: n = 16^n16 8^n8 4^n4 2^n2 3^n3 with as many radix-16
+// stages as the power of two allows and at most one of radix 8, 4 or 2;
+// packed as n16 | n8 << 6 | n4 << 12 | n2 << 18 | n3 << 24.
 static bool factor_radices(int n, uint32_t *code, int *nstages)
 {
-    uint32_t n4 = 0, n2 = 0, n3 = 0;
-    while (n % 4 == 0) { ++n4; n /= 4; }
-    while (n % 2 == 0) { ++n2; n /= 2; }
+    uint32_t p2 = 0, n3 = 0;
+    while (n % 2 == 0) { ++p2; n /= 2; }
     while (n % 3 == 0) { ++n3; n /= 3; }
     if (n != 1) return false;
-    *code = n4 | (n2 << 8) | (n3 << 16);
-    *nstages = (int)(n4 + n2 + n3);
+    const uint32_t n16 = p2 / 4, r = p2 % 4;
+    const uint32_t n8 = r == 3, n4 = r == 2, n2 = r == 1;
+    *code = n16 | (n8 << 6) | (n4 << 12) | (n2 << 18) | (n3 << 24);
+    *nstages = (int)(n16 + n8 + n4 + n2 + n3);
     return true;
 }
 
