@@ -130,13 +130,16 @@ bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *
                              const size_t *ws_bytes, int32_t iters_per_graph, void *stream, bfm_result *results);
 
 /* Autotuner: times the candidate launch shapes of the c-transform line
- * kernel for every axis of the plan (points per lane 8 or 16; on strided
- * axes one or four lines per workgroup; one line group per workgroup or
+ * kernel for every axis of the plan (points per lane 4, 8 or 16; on strided
+ * axes one, two or four lines per workgroup; one line group per workgroup or
  * persistent prefetching workgroups), axis by axis in the order of a
  * transform, on `sample` (a device potential of N elements, e.g. the
  * current phi; NULL: a smooth test potential), and keeps the fastest in the
- * plan (and in a process-wide table).  Optional: untuned plans use built-in
- * shapes.  Synchronises `stream`; overwrites the workspace. */
+ * plan (and in a process-wide table).  In 2D it then times the whole
+ * transform with that choice against both axes on the persistent kernel
+ * (which passes a column-blocked intermediate between the two passes) and
+ * keeps the faster.  Optional: untuned plans use built-in shapes.
+ * Synchronises `stream`; overwrites the workspace. */
 bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *workspace, size_t ws_bytes, void *stream);
 
 /* The launch shapes the plan uses, three int32 per axis a < 3:
@@ -147,10 +150,11 @@ bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg9);
 
 /* Sets the launch shapes (same layout as bfm_plan_tuning), e.g. to reuse a
  * tuning from an earlier process.  BFM_EINVAL for values outside the listed
- * choices or too few points per lane for the axis (C * 256 < n).  A mode-2
+ * choices or too few points per lane for the axis (C * 1024 < n).  A mode-2
  * (persistent) choice on a layout it does not apply to (n % 4 != 0 on the
- * last axis, a strided axis with one line per workgroup or inner % 4 != 0,
- * fields not 16-byte aligned) makes later calls fail with BFM_EDEVICE. */
+ * last axis; on a strided axis one line per workgroup, four lines with
+ * inner % 4 != 0 or two with inner odd; fields not 16-byte aligned) makes
+ * later calls fail with BFM_EDEVICE. */
 bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9);
 
 /* Primitive: quadratic-cost c-transform on the grid (Definition of the

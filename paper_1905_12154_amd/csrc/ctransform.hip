@@ -63,6 +63,29 @@ template <typename T> struct vec4;
 template <> struct vec4<float> { using type = float4; };
 template <> struct vec4<double> { using type = double4; };
 
+// W-wide vectors (W = 2 or 4) of the strided passes: one per grid row for W
+// adjacent lines.
+template <typename T, int W> struct vecw;
+template <> struct vecw<float, 4> { using type = float4; };
+template <> struct vecw<double, 4> { using type = double4; };
+template <> struct vecw<float, 2> { using type = float2; };
+template <> struct vecw<double, 2> { using type = double2; };
+template <typename V> __device__ __forceinline__ auto vget(const V &x, int e) {
+    if constexpr (sizeof(V) / sizeof(x.x) == 4) return e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w;
+    else return e == 0 ? x.x : x.y;
+}
+template <typename V, typename T> __device__ __forceinline__ void vset(V &x, int e, T val) {
+    if constexpr (sizeof(V) / sizeof(x.x) == 4) {
+        if (e == 0) x.x = val; else if (e == 1) x.y = val; else if (e == 2) x.z = val; else x.w = val;
+    } else {
+        if (e == 0) x.x = val; else x.y = val;
+    }
+}
+
+// Largest workgroup a (C, LPB) instantiation is launched with: lines of at
+// most 4096 points take tpl <= 4096 / C lanes (a power of two).
+constexpr int ct_max_threads(int C, int LPB) { return LPB * (4096 / C) < 1024 ? LPB * (4096 / C) : 1024; }
+
 // Wait for the lanes of one wave around LDS traffic, without a workgroup
 // barrier: a wave's LDS operations are performed in issue order, so only the
 // compiler has to be kept from moving accesses across this point.
@@ -79,8 +102,8 @@ __device__ __forceinline__ void line_sync(int tpl) {
     else __syncthreads();
 }
 
-// Steps 2-5 for the line of this lane, whose values are staged in v (LDS);
-// on return u holds the output at the lane's points [j0, j1).
+// Steps 2-5 for the line of this lane, whose values are staged in v (LDS)
+// and, for the lane's points [j0, j1), in u; on return u holds the output.
 // Touches only this line's LDS (v, pv/nx, GH/GT) and wave_tot; all lanes of
 // the workgroup call it (its block barriers are uniform).
 template <typename T, int C>
@@ -88,25 +111,31 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                                              int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
 {
     const T n2 = T(n) * T(n);
-    // 2. lane-local lower hull of points [j0, j1)
+    // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
+    //    entries live in registers (u holds the lane's values), so only pops
+    //    read LDS
     if (j0 < j1) {
-        int top = j0;
-        T utop = v[padi(j0)];
+        int top = j0, a = -1;
+        T utop = u[0], ua = T(0);
         pv[padi(j0)] = kNone;
-        for (int j = j0 + 1; j < j1; ++j) {
-            const T uj = v[padi(j)];
-            int a = pv[padi(top)];
-            while (a >= 0) {
-                const T ua = v[padi(a)];
-                if (!above_chord(a, top, j, ua, utop, uj, n2)) break;
-                pv[padi(top)] = kDead;
-                top = a;
-                utop = ua;
-                a = pv[padi(top)];
+#pragma unroll
+        for (int c = 1; c < C; ++c) {
+            const int j = j0 + c;
+            if (j < j1) {
+                const T uj = u[c];
+                while (a >= 0 && above_chord(a, top, j, ua, utop, uj, n2)) {
+                    pv[padi(top)] = kDead;
+                    top = a;
+                    utop = ua;
+                    a = pv[padi(top)];
+                    if (a >= 0) ua = v[padi(a)];
+                }
+                pv[padi(j)] = (short)top;
+                a = top;
+                ua = utop;
+                top = j;
+                utop = uj;
             }
-            pv[padi(j)] = (short)top;
-            top = j;
-            utop = uj;
         }
         int k = top;
         nx[padi(k)] = kNone;
@@ -241,7 +270,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
 
 // One group of LPB lines per workgroup: any line length, stride or alignment.
 template <typename T, int C, int LPB>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(ct_max_threads(C, LPB))
 ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
                 T sgn, T h, const int32_t *__restrict__ done)
 {
@@ -310,9 +339,12 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
                 vals[ll * NP + padi(j)] = LL < nlines ? sgn * in[line_base(LL, n, inner) + (long long)j * inner] : T(0);
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
     }
-    if (inner == 1) line_sync(tpl);   // rows: every lane staged only its own line
-    else __syncthreads();
+    // rows: each lane staged only its own points, which the local hull reads
+    // back itself; the merge rounds synchronise before reading other lanes'
 
     ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
 
@@ -365,14 +397,24 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
 // the C values each lane needs for the next group (tpl * C >= n, so a lane's
 // share of LPB * n values is at most C) are loaded into registers while the
 // current group is transformed from LDS.
-template <typename T, int C, int LPB, bool STRIDED>
-__global__ void __launch_bounds__(1024)
+//
+// BLK selects the column-blocked layout of a 2D field (rows r < R, columns
+// c < K, K % 4 == 0): element (r, c) at (c / 4) * 4 R + 4 r + c % 4, i.e. each
+// group of four columns is one contiguous run of R 16-byte vectors.  The
+// strided pass over the columns (nlines = inner = K, n = R) writes its output
+// in that layout, so every group's output is one contiguous 16 R-byte run;
+// the contiguous pass over the rows (nlines = R, n = K) reads it.
+template <typename T, int C, int LPB, bool STRIDED, bool BLK>
+__global__ void __launch_bounds__(ct_max_threads(C, LPB))
 ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
                    T sgn, T h, const int32_t *__restrict__ done)
 {
-    static_assert(C % 4 == 0 && (!STRIDED || LPB == 4), "vector layout");
+    static_assert(C % 4 == 0 && (!STRIDED || LPB == 4 || LPB == 2) && (!BLK || !STRIDED || LPB == 4),
+                  "vector layout");
     if (done != nullptr && *done) return;
     using V4 = typename vec4<T>::type;
+    constexpr int W = STRIDED ? LPB : 4;   // vector width of the global accesses
+    using VW = typename vecw<T, W>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int NP = padded_len(n);
     T *vals = reinterpret_cast<T *>(smem);
@@ -389,20 +431,27 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
     int *GH = grp + l * 2 * tpl;
     const long long step = (long long)gridDim.x * LPB;
 
-    V4 pf[C / 4] = {};
+    VW pf[C / W] = {};
     auto fetch = [&](long long G0) {
-        if (!STRIDED) {
+        if constexpr (!STRIDED) {
             const long long L = G0 + l;
-            const V4 *src = reinterpret_cast<const V4 *>(in + L * n + jb);
+            if (BLK) {   // row L of the column-blocked layout: vector q at (jb + 4q) R + 4L
 #pragma unroll
-            for (int q = 0; q < C / 4; ++q)
-                if (L < nlines && jb + 4 * q < n) pf[q] = src[q];
+                for (int q = 0; q < C / 4; ++q)
+                    if (L < nlines && jb + 4 * q < n)
+                        pf[q] = *reinterpret_cast<const V4 *>(in + (long long)(jb + 4 * q) * nlines + 4 * L);
+            } else {
+                const V4 *src = reinterpret_cast<const V4 *>(in + L * n + jb);
+#pragma unroll
+                for (int q = 0; q < C / 4; ++q)
+                    if (L < nlines && jb + 4 * q < n) pf[q] = src[q];
+            }
         } else {
             const T *src = in + line_base(G0, n, inner);
 #pragma unroll
-            for (int q = 0; q < C / 4; ++q) {
+            for (int q = 0; q < C / W; ++q) {
                 const int j = tid + q * nthr;
-                if (j < n) pf[q] = *reinterpret_cast<const V4 *>(src + (long long)j * inner);
+                if (j < n) pf[q] = *reinterpret_cast<const VW *>(src + (long long)j * inner);
             }
         }
     };
@@ -417,7 +466,7 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
         const int j1 = min(j0 + C, n);
         const long long L = G0 + l;
         T u[C];
-        if (!STRIDED) {
+        if constexpr (!STRIDED) {
 #pragma unroll
             for (int q = 0; q < C / 4; ++q) {
                 u[4 * q] = sgn * pf[q].x;
@@ -428,26 +477,27 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (j0 + c < j1) v[padi(j0 + c)] = u[c];
-            line_sync(tpl);
+            // no barrier: the local hull reads only the lane's own points and
+            // the merge rounds synchronise before reading other lanes'
         } else {
 #pragma unroll
-            for (int q = 0; q < C / 4; ++q) {
+            for (int q = 0; q < C / W; ++q) {
                 const int j = tid + q * nthr;
                 if (j < n) {
                     const int pj = padi(j);
-                    vals[0 * NP + pj] = sgn * pf[q].x;
-                    vals[1 * NP + pj] = sgn * pf[q].y;
-                    vals[2 * NP + pj] = sgn * pf[q].z;
-                    vals[3 * NP + pj] = sgn * pf[q].w;
+#pragma unroll
+                    for (int e = 0; e < W; ++e) vals[e * NP + pj] = sgn * vget(pf[q], e);
                 }
             }
             __syncthreads();
+#pragma unroll
+            for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
         }
         if (G0 + step < nlines) fetch(G0 + step);   // in flight during the transform
 
         ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
 
-        if (!STRIDED) {
+        if constexpr (!STRIDED) {
             if (L < nlines && j0 < j1) {
                 V4 *dst = reinterpret_cast<V4 *>(out + L * n + j0);
 #pragma unroll
@@ -466,12 +516,16 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
             for (int c = 0; c < C; ++c)
                 if (j0 + c < j1) v[padi(j0 + c)] = u[c];
             __syncthreads();
-            T *dst = out + line_base(G0, n, inner);
+            // plain: row j of the group at line_base + j * inner; blocked: the
+            // group's run starts at G0 * n (G0 = 4 x group index), 4 per row
+            T *dst = BLK ? out + G0 * n : out + line_base(G0, n, inner);
+            const long long rs = BLK ? 4 : inner;
             for (int j = tid; j < n; j += nthr) {
                 const int pj = padi(j);
-                V4 x;
-                x.x = vals[0 * NP + pj]; x.y = vals[1 * NP + pj]; x.z = vals[2 * NP + pj]; x.w = vals[3 * NP + pj];
-                *reinterpret_cast<V4 *>(dst + (long long)j * inner) = x;
+                VW x;
+#pragma unroll
+                for (int e = 0; e < W; ++e) vset(x, e, vals[e * NP + pj]);
+                *reinterpret_cast<VW *>(dst + (long long)j * rs) = x;
             }
             __syncthreads();
         }
@@ -503,8 +557,14 @@ static CtShape ct_shape(int n, bool strided, size_t esz, CtCfg cfg = CtCfg{})
     s.tpl = 1;
     while (s.tpl < need) s.tpl <<= 1;
     if (strided) {
-        s.lpb = ct_smem_for(n, s.tpl, 4, esz) <= kCtLdsBudget ? 4 : 1;
-        if (cfg.lpb == 1) s.lpb = 1;
+        // the widest group of 4 or 2 lines that fits LDS and 1024 lanes (or the requested width)
+        const int want = cfg.lpb > 0 ? cfg.lpb : 4;
+        s.lpb = 1;
+        for (int w = want; w > 1; w >>= 1)
+            if (ct_smem_for(n, s.tpl, w, esz) <= kCtLdsBudget && w * s.tpl <= 1024) {
+                s.lpb = w;
+                break;
+            }
     } else {
         s.lpb = s.tpl >= 256 ? 1 : 256 / s.tpl;
         if (s.lpb > 64) s.lpb = 64;
@@ -548,40 +608,48 @@ static hipError_t allow_smem(KernelT fn, size_t smem, bool &done_flag)
     return hipSuccess;
 }
 
+template <typename T, int C, int LPB, bool STRIDED, bool BLK>
+static hipError_t launch_pf(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads, T sgn,
+                            const int32_t *done, hipStream_t stream)
+{
+    static bool attr = false;
+    const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
+    const long long groups = (nlines + LPB - 1) / LPB;
+    auto fn = ct_lines_pf_kernel<T, C, LPB, STRIDED, BLK>;
+    hipError_t e = allow_smem(fn, smem, attr);
+    if (e != hipSuccess) return e;
+    long long blocks = resident_blocks((const void *)fn, threads, smem);
+    if (blocks > groups) blocks = groups;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner, nlines, tpl, sgn,
+                       T(1.0) / T(n), done);
+    return hipGetLastError();
+}
+
+// blk: the strided pass writes, the contiguous pass reads, the column-blocked
+// layout of a 2D field (only with the persistent kernel).
 template <typename T, int C, int LPB>
 static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads,
-                                 T sgn, const int32_t *done, hipStream_t stream, bool persistent)
+                                 T sgn, const int32_t *done, hipStream_t stream, bool persistent, bool blk)
 {
     const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
     const long long groups = (nlines + LPB - 1) / LPB;
     const T h = T(1.0) / T(n);
     if (persistent) {
         if constexpr (LPB == 4) {
-            if (inner > 1) {
-                static bool attr = false;
-                auto fn = ct_lines_pf_kernel<T, C, 4, true>;
-                hipError_t e = allow_smem(fn, smem, attr);
-                if (e != hipSuccess) return e;
-                long long blocks = resident_blocks((const void *)fn, threads, smem);
-                if (blocks > groups) blocks = groups;
-                hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner,
-                                   nlines, tpl, sgn, h, done);
-                return hipGetLastError();
-            }
+            if (inner > 1)
+                return blk ? launch_pf<T, C, 4, true, true>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream)
+                           : launch_pf<T, C, 4, true, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream);
         }
-        if (inner == 1) {
-            static bool attr = false;
-            auto fn = ct_lines_pf_kernel<T, C, LPB, false>;
-            hipError_t e = allow_smem(fn, smem, attr);
-            if (e != hipSuccess) return e;
-            long long blocks = resident_blocks((const void *)fn, threads, smem);
-            if (blocks > groups) blocks = groups;
-            hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner, nlines,
-                               tpl, sgn, h, done);
-            return hipGetLastError();
+        if constexpr (LPB == 2) {
+            if (inner > 1 && !blk)
+                return launch_pf<T, C, 2, true, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream);
         }
+        if (inner == 1)
+            return blk ? launch_pf<T, C, LPB, false, true>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream)
+                       : launch_pf<T, C, LPB, false, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream);
         return hipErrorInvalidValue;
     }
+    if (blk) return hipErrorInvalidValue;
     static bool attr = false;
     hipError_t e = allow_smem(ct_lines_kernel<T, C, LPB>, smem, attr);
     if (e != hipSuccess) return e;
@@ -597,34 +665,63 @@ static bool ct_persistent_ok(int n, int inner, int lpb, const void *in, const vo
 {
     if ((((uintptr_t)in | (uintptr_t)out) & 15) != 0) return false;
     if (inner == 1) return (n & 3) == 0;
-    return lpb == 4 && (inner & 3) == 0;
+    return (lpb == 4 && (inner & 3) == 0) || (lpb == 2 && (inner & 1) == 0);
+}
+
+// Whether an axis pass runs the persistent kernel under `cfg`.
+template <typename T>
+static bool ct_uses_persistent(int n, int inner, const void *in, const void *out, CtCfg cfg)
+{
+    const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
+    return ct_persistent_ok(n, inner, s.lpb, in, out) && (cfg.pers == 2 || (cfg.pers == 0 && sizeof(T) == 4));
+}
+
+template <typename T>
+static hipError_t launch_ct_axis_blk(const T *in, T *out, int n, int inner, long long nlines, T sgn,
+                                     const int32_t *done, hipStream_t stream, CtCfg cfg, bool blk)
+{
+    const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
+    if (s.tpl > 1024 || s.threads > ct_max_threads(s.C, s.lpb)) return hipErrorInvalidValue;
+    const bool ok = ct_persistent_ok(n, inner, s.lpb, in, out);
+    if (cfg.pers == 2 && !ok) return hipErrorInvalidValue;
+    const bool pers = ok && (cfg.pers == 2 || (cfg.pers == 0 && sizeof(T) == 4));
+    if (blk && !pers) return hipErrorInvalidValue;
+#define BFM_CT_CASE(CC, LL)                                                                               \
+    if (s.C == CC && s.lpb == LL)                                                                         \
+        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream, pers, blk);
+    BFM_CT_CASE(16, 1) BFM_CT_CASE(16, 4) BFM_CT_CASE(8, 1) BFM_CT_CASE(8, 2) BFM_CT_CASE(8, 4)
+    BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
+    BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64) BFM_CT_CASE(4, 1)
+    BFM_CT_CASE(4, 2) BFM_CT_CASE(4, 4) BFM_CT_CASE(4, 8) BFM_CT_CASE(4, 16) BFM_CT_CASE(4, 32) BFM_CT_CASE(4, 64)
+#undef BFM_CT_CASE
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
                           const int32_t *done, hipStream_t stream, CtCfg cfg)
 {
-    const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
-    if (s.tpl > 256 || s.threads > 1024) return hipErrorInvalidValue;
-    const bool ok = ct_persistent_ok(n, inner, s.lpb, in, out);
-    if (cfg.pers == 2 && !ok) return hipErrorInvalidValue;
-    const bool pers = ok && (cfg.pers == 2 || (cfg.pers == 0 && sizeof(T) == 4));
-#define BFM_CT_CASE(CC, LL)                                                                               \
-    if (s.C == CC && s.lpb == LL)                                                                         \
-        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream, pers);
-    BFM_CT_CASE(16, 1) BFM_CT_CASE(16, 4) BFM_CT_CASE(8, 1) BFM_CT_CASE(8, 2) BFM_CT_CASE(8, 4)
-    BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
-    BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64)
-#undef BFM_CT_CASE
-    return hipErrorInvalidValue;
+    return launch_ct_axis_blk<T>(in, out, n, inner, nlines, sgn, done, stream, cfg, false);
 }
 
-// Full c-transform of a field: out = in^c, axis ndim-1 first (u = -in), then
-// each earlier axis on the running result.
+// Full c-transform of a field: out = in^c.  The axes are independent
+// minimisations, so any order gives the same minimum.  Default order: axis
+// ndim-1 first (u = -in), then each earlier axis on the running result.  In
+// 2D, when both passes run the persistent kernel and `scratch` (N words) is
+// given, the columns go first and write the column-blocked layout into
+// scratch, and the rows read it: both passes then write whole contiguous runs.
 template <typename T>
 hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
-                            const CtCfg *cfg)
+                            const CtCfg *cfg, T *scratch)
 {
+    const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
+    if (g.ndim == 2 && scratch != nullptr && scratch != in && scratch != out && (g.n[1] & 3) == 0 &&
+        ct_uses_persistent<T>(g.n[0], g.n[1], in, scratch, c0) && ct_shape(g.n[0], true, sizeof(T), c0).lpb == 4 &&
+        ct_uses_persistent<T>(g.n[1], 1, scratch, out, c1)) {
+        hipError_t e = launch_ct_axis_blk<T>(in, scratch, g.n[0], g.n[1], g.n[1], T(-1), done, stream, c0, true);
+        if (e != hipSuccess) return e;
+        return launch_ct_axis_blk<T>(scratch, out, g.n[1], 1, g.n[0], T(1), done, stream, c1, true);
+    }
     for (int a = g.ndim - 1; a >= 0; --a) {
         const int n = g.n[a];
         const int inner = (int)g.stride[a];
@@ -642,9 +739,9 @@ template hipError_t launch_ct_axis<float>(const float *, float *, int, int, long
 template hipError_t launch_ct_axis<double>(const double *, double *, int, int, long long, double,
                                            const int32_t *, hipStream_t, CtCfg);
 template hipError_t ctransform_field<float>(const Grid &, const float *, float *, const int32_t *, hipStream_t,
-                                            const CtCfg *);
+                                            const CtCfg *, float *);
 template hipError_t ctransform_field<double>(const Grid &, const double *, double *, const int32_t *, hipStream_t,
-                                             const CtCfg *);
+                                             const CtCfg *, double *);
 template size_t ct_smem_bytes<float>(int, int, int);
 template size_t ct_smem_bytes<double>(int, int, int);
 

@@ -16,7 +16,7 @@ struct AxisPlan {
 
 // c-transform (ctransform.hip).  CtCfg overrides the launch shape of one
 // axis (0 = built-in choice): C points per lane, lines per workgroup on a
-// strided axis (1 or 4), pers = 1 one line group per workgroup, 2 persistent
+// strided axis (1, 2 or 4), pers = 1 one line group per workgroup, 2 persistent
 // workgroups with prefetch (aligned layouts only).
 struct CtCfg {
     int C = 0;
@@ -25,7 +25,7 @@ struct CtCfg {
 };
 template <typename T>
 hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
-                            const CtCfg *cfg = nullptr);
+                            const CtCfg *cfg = nullptr, T *scratch = nullptr);
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
                           const int32_t *done, hipStream_t stream, CtCfg cfg = CtCfg{});

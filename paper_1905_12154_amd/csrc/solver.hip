@@ -358,7 +358,7 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     T *pc = (T *)w.pc, *rho = (T *)w.rho, *F = (T *)w.f;
     const CtrlParams cp = ctrl_params(P);
     hipError_t e;
-    if ((e = ctransform_field<T>(g, p, pc, done, s, P->ct_cfg)) != hipSuccess) return e;
+    if ((e = ctransform_field<T>(g, p, pc, done, s, P->ct_cfg, F)) != hipSuccess) return e;   // F is free here
     if (head_dot &&
         (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
@@ -371,7 +371,7 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
         return e;
     if (head_only) return hipSuccess;
     if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
-    if ((e = ctransform_field<T>(g, p, q, done, s, P->ct_cfg)) != hipSuccess) return e;
+    if ((e = ctransform_field<T>(g, p, q, done, s, P->ct_cfg, F)) != hipSuccess) return e;   // F consumed above
     if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
         return e;
     return launch_ctrl(w.st, w.part, w.gpart, step_mode, cp, w.trace, s);
@@ -734,10 +734,10 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
             continue;
         }
         std::vector<CtCfg> cand;
-        for (int C : {8, 16})
-            for (int lpb : inner > 1 ? std::vector<int>{1, 4} : std::vector<int>{0})
+        for (int C : {4, 8, 16})
+            for (int lpb : inner > 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{0})
                 for (int pers : {1, 2}) {
-                    if ((n + C - 1) / C > 256) continue;
+                    if ((n + C - 1) / C > 1024) continue;
                     CtCfg c;
                     c.C = C;
                     c.lpb = lpb;
@@ -775,6 +775,42 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
         }
         std::swap(f, nxt);
     }
+    // 2D: the per-axis choice against both axes on the persistent kernel,
+    // which lets the transform pass the column-blocked intermediate; timed
+    // as whole transforms
+    if (out == BFM_OK && g.ndim == 2 && (P->ct_cfg[0].pers != 2 || P->ct_cfg[1].pers != 2)) {
+        const T *src = sample;
+        if (src == nullptr) {
+            hipLaunchKernelGGL((tune_field_kernel<T>), dim3(1024), dim3(256), 0, s, (T *)w.f, g);
+            HIP_TRY(hipGetLastError());
+            src = (const T *)w.f;
+        }
+        CtCfg both[3] = {P->ct_cfg[0], P->ct_cfg[1], P->ct_cfg[2]};
+        both[0].pers = both[1].pers = 2;
+        T *scratch = src == (const T *)w.f ? (T *)w.rho : (T *)w.f;
+        float best = 1e30f;
+        int pick = -1;
+        for (int c = 0; c < 2; ++c) {
+            const CtCfg *cf = c == 0 ? P->ct_cfg : both;
+            hipError_t e = ctransform_field<T>(g, src, o, nullptr, s, cf, scratch);   // warm-up
+            if (e != hipSuccess) continue;
+            (void)hipEventRecord(a, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = ctransform_field<T>(g, src, o, nullptr, s, cf, scratch);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess || e != hipSuccess) continue;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        if (pick == 1) {
+            P->ct_cfg[0] = both[0];
+            P->ct_cfg[1] = both[1];
+        }
+        (void)hipGetLastError();
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return out;
@@ -797,10 +833,11 @@ extern "C" bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9)
     CtCfg c[3];
     for (int a = 0; a < 3; ++a) {
         const int C = cfg9[3 * a], lpb = cfg9[3 * a + 1], pers = cfg9[3 * a + 2];
-        if ((C != 0 && C != 8 && C != 16) || (lpb != 0 && lpb != 1 && lpb != 4) || pers < 0 || pers > 2)
-            return fail(BFM_EINVAL, "tuning of axis %d: points per lane %d (0, 8, 16), lines %d (0, 1, 4), mode %d (0-2)",
-                        a, C, lpb, pers);
-        if (a < plan->g.ndim && C != 0 && (plan->g.n[a] + C - 1) / C > 256)
+        if ((C != 0 && C != 4 && C != 8 && C != 16) || (lpb != 0 && lpb != 1 && lpb != 2 && lpb != 4) || pers < 0 || pers > 2)
+            return fail(BFM_EINVAL,
+                        "tuning of axis %d: points per lane %d (0, 4, 8, 16), lines %d (0, 1, 2, 4), mode %d (0-2)", a, C,
+                        lpb, pers);
+        if (a < plan->g.ndim && C != 0 && (plan->g.n[a] + C - 1) / C > 1024)
             return fail(BFM_EINVAL, "tuning of axis %d: %d points per lane do not cover %d points", a, C, plan->g.n[a]);
         c[a].C = C;
         c[a].lpb = lpb;
@@ -832,9 +869,11 @@ extern "C" bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, v
     if (st != BFM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (plan->prm.dtype == BFM_F64)
-        HIP_TRY(ctransform_field<double>(plan->g, (const double *)in, (double *)out, nullptr, s, plan->ct_cfg));
+        HIP_TRY(ctransform_field<double>(plan->g, (const double *)in, (double *)out, nullptr, s, plan->ct_cfg,
+                                         (double *)w.f));
     else
-        HIP_TRY(ctransform_field<float>(plan->g, (const float *)in, (float *)out, nullptr, s, plan->ct_cfg));
+        HIP_TRY(ctransform_field<float>(plan->g, (const float *)in, (float *)out, nullptr, s, plan->ct_cfg,
+                                        (float *)w.f));
     return BFM_OK;
 }
 
