@@ -785,13 +785,25 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
             HIP_TRY(hipGetLastError());
             src = (const T *)w.f;
         }
-        CtCfg both[3] = {P->ct_cfg[0], P->ct_cfg[1], P->ct_cfg[2]};
-        both[0].pers = both[1].pers = 2;
+        // candidates: the per-axis choice, then both axes persistent with the
+        // tuned column shape and each row width
+        CtCfg cand[4][3];
+        int ncand = 0;
+        for (int a = 0; a < 3; ++a) cand[0][a] = P->ct_cfg[a];
+        ncand = 1;
+        for (int C : {8, 16}) {
+            if ((g.n[1] + C - 1) / C > 1024) continue;
+            for (int a = 0; a < 3; ++a) cand[ncand][a] = P->ct_cfg[a];
+            cand[ncand][0].pers = 2;
+            cand[ncand][1].pers = 2;
+            cand[ncand][1].C = C;
+            ++ncand;
+        }
         T *scratch = src == (const T *)w.f ? (T *)w.rho : (T *)w.f;
         float best = 1e30f;
         int pick = -1;
-        for (int c = 0; c < 2; ++c) {
-            const CtCfg *cf = c == 0 ? P->ct_cfg : both;
+        for (int c = 0; c < ncand; ++c) {
+            const CtCfg *cf = cand[c];
             hipError_t e = ctransform_field<T>(g, src, o, nullptr, s, cf, scratch);   // warm-up
             if (e != hipSuccess) continue;
             (void)hipEventRecord(a, s);
@@ -805,9 +817,9 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
                 pick = c;
             }
         }
-        if (pick == 1) {
-            P->ct_cfg[0] = both[0];
-            P->ct_cfg[1] = both[1];
+        if (pick > 0) {
+            P->ct_cfg[0] = cand[pick][0];
+            P->ct_cfg[1] = cand[pick][1];
         }
         (void)hipGetLastError();
     }
