@@ -144,6 +144,18 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
                                           const cpx<T> *__restrict__ tw) {
     constexpr int NB = (VMAX + R - 1) / R;
     const int m = n / R;
+    const int tstep = n / (p * R);
+    // twiddles w^t, w = exp(-2 pi i k / (p R)): for radix 4, 8 and 16 one
+    // table load of w and powers by products (w^2t = (w^t)^2,
+    // w^(t+1) = w^t w: at most 6 products deep); the first stage (p = 1)
+    // needs none.  Loaded before the barrier so the latency overlaps.
+    cpx<T> w1[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int i = lt + q * bd;
+        w1[q] = {T(1), T(0)};
+        if (R >= 4 && p > 1 && i < m) w1[q] = tw[(i % p) * tstep];
+    }
     cpx<T> x[NB][R];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -154,14 +166,24 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
         }
     }
     __syncthreads();
-    const int tstep = n / (p * R);
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int i = lt + q * bd;
         if (i < m) {
             const int k = i % p;
+            if constexpr (R >= 4) {
+                if (p > 1) {
+                    cpx<T> wp[R];
+                    wp[1] = w1[q];
 #pragma unroll
-            for (int t = 1; t < R; ++t) x[q][t] = cmul(x[q][t], tw[t * k * tstep]);
+                    for (int t = 2; t < R; ++t) wp[t] = (t & 1) ? cmul(wp[t - 1], wp[1]) : cmul(wp[t / 2], wp[t / 2]);
+#pragma unroll
+                    for (int t = 1; t < R; ++t) x[q][t] = cmul(x[q][t], wp[t]);
+                }
+            } else {
+#pragma unroll
+                for (int t = 1; t < R; ++t) x[q][t] = cmul(x[q][t], tw[t * k * tstep]);
+            }
             small_dft<T, R>(x[q]);
             const int j = (i - k) * R + k;
 #pragma unroll
