@@ -14,7 +14,7 @@
 // and sum mu phi^c (the second term of J).
 //
 // Deposition: source cells are processed by compact tiles (32 x 32 in 2D,
-// 8 x 8 x 16 in 3D).  Where the map compresses mass, many sources of a tile
+// 4 x 8 x 8 in 3D).  Where the map compresses mass, many sources of a tile
 // land on few target cells, and global atomics on the same addresses
 // serialise; so the workgroup first accumulates its deposits in an LDS box
 // covering all its targets (LDS atomics) and then adds each non-zero box
@@ -26,11 +26,13 @@
 
 namespace bfm {
 
-template <typename T> constexpr int box_cap() { return 8192 / (int)sizeof(T); }   // LDS box cells (8 KB)
+// LDS box cells: 8 KB in 2D, 16 KB in 3D (a 3D tile's targets spread over
+// a box that grows with the cube of the local expansion of the map)
+template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 8192) / (int)sizeof(T); }
 
 template <int D> struct Tile;
 template <> struct Tile<2> { static constexpr int s[2] = {32, 32}; static constexpr int cells = 1024; };
-template <> struct Tile<3> { static constexpr int s[3] = {8, 8, 16}; static constexpr int cells = 1024; };
+template <> struct Tile<3> { static constexpr int s[3] = {4, 8, 8}; static constexpr int cells = 256; };
 
 // Persistent workgroups walk the tiles in a grid-stride loop; a tile without
 // mass is skipped after one vote.  Partial sums are one per workgroup.
@@ -42,7 +44,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
 {
     if (done != nullptr && *done) return;
     constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
-    constexpr int kBoxCap = box_cap<T>();
+    constexpr int kBoxCap = box_cap<T, D>();
     __shared__ double sh[kRedBlock / kWave];
     __shared__ T box[kBoxCap];
     __shared__ int bnd[2 * D];
