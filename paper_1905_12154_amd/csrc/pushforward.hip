@@ -14,7 +14,7 @@
 // and sum mu phi^c (the second term of J).
 //
 // Deposition: source cells are processed by compact tiles (32 x 32 in 2D,
-// 4 x 8 x 8 in 3D).  Where the map compresses mass, many sources of a tile
+// 8 x 8 x 8 in 3D).  Where the map compresses mass, many sources of a tile
 // land on few target cells, and global atomics on the same addresses
 // serialise; so the workgroup first accumulates its deposits in an LDS box
 // covering all its targets (LDS atomics) and then adds each non-zero box
@@ -32,7 +32,7 @@ template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 
 
 template <int D> struct Tile;
 template <> struct Tile<2> { static constexpr int s[2] = {32, 32}; static constexpr int cells = 1024; };
-template <> struct Tile<3> { static constexpr int s[3] = {4, 8, 8}; static constexpr int cells = 256; };
+template <> struct Tile<3> { static constexpr int s[3] = {8, 8, 8}; static constexpr int cells = 512; };
 
 // Persistent workgroups walk the tiles in a grid-stride loop; a tile without
 // mass is skipped after one vote.  Partial sums are one per workgroup.
@@ -47,12 +47,19 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
     constexpr int kBoxCap = box_cap<T, D>();
     __shared__ double sh[kRedBlock / kWave];
     __shared__ T box[kBoxCap];
-    __shared__ int bnd[2 * D];
+    __shared__ int bnd[2][2 * D];   // box bounds, alternating between consecutive tiles with mass
 
     int ntile[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
     double accP = 0.0, accJ = 0.0;
+    for (int e = threadIdx.x; e < kBoxCap; e += kRedBlock) box[e] = T(0);
+    if (threadIdx.x < 2 * D) {
+        bnd[threadIdx.x / D][threadIdx.x % D] = 0x7fffffff;
+        bnd[threadIdx.x / D][D + threadIdx.x % D] = -1;
+    }
+    __syncthreads();
+    int kused = 0;   // tiles with mass processed so far by this workgroup
 
     for (long long tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
         int tc[D];
@@ -84,11 +91,14 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             any = any || s[q] != T(0);
         }
         if (!__syncthreads_or(any) && Tout == nullptr) continue;
+        // this tile's bounds; the other set was last read before the barrier
+        // above, so it is reset here for the next tile
+        int *bb = bnd[kused & 1];
         if (threadIdx.x < D) {
-            bnd[threadIdx.x] = 0x7fffffff;
-            bnd[D + threadIdx.x] = -1;
+            bnd[(kused + 1) & 1][threadIdx.x] = 0x7fffffff;
+            bnd[(kused + 1) & 1][D + threadIdx.x] = -1;
         }
-        __syncthreads();
+        ++kused;
 
         T wup[PER][D];
         int lo[PER][D];
@@ -156,23 +166,22 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                 bmax[a] = max(bmax[a], __shfl_xor(bmax[a], o, kWave));
             }
             if ((threadIdx.x & (kWave - 1)) == 0 && bmax[a] >= 0) {
-                atomicMin(&bnd[a], bmin[a]);
-                atomicMax(&bnd[D + a], bmax[a]);
+                atomicMin(&bb[a], bmin[a]);
+                atomicMax(&bb[D + a], bmax[a]);
             }
         }
         __syncthreads();
-        if (rho == nullptr || bnd[D] < 0) continue;   // uniform: read after the barrier
+        if (rho == nullptr || bb[D] < 0) continue;   // uniform: read after the barrier
         int bl[D], bs[D];
         long long area = 1;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            bl[a] = bnd[a];
-            bs[a] = bnd[D + a] - bnd[a] + 1;
+            bl[a] = bb[a];
+            bs[a] = bb[D + a] - bb[a] + 1;
             area *= bs[a];
         }
         if (area <= kBoxCap) {
-            for (int e = threadIdx.x; e < area; e += kRedBlock) box[e] = T(0);
-            __syncthreads();
+            // the box is all zero here: cleared at the start and by every flush
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 if (s[q] == T(0)) continue;
@@ -192,6 +201,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             __syncthreads();
             for (int e = threadIdx.x; e < area; e += kRedBlock) {
                 const T v = box[e];
+                box[e] = T(0);
                 if (v != T(0)) {
                     int r = e;
                     long long gi = 0;
@@ -221,7 +231,8 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                 }
             }
         }
-        __syncthreads();   // box and bnd are reused by the next tile
+        // no barrier: the next tile deposits into the box only after its own
+        // two barriers, which this flush precedes
     }
     const double P = block_reduce<R_SUM>(accP, sh);
     const double J = block_reduce<R_SUM>(accJ, sh);
