@@ -407,11 +407,14 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
 template <typename T, int C, int LPB, bool STRIDED, bool BLK>
 __global__ void __launch_bounds__(ct_max_threads(C, LPB))
 ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
-                   T sgn, T h, const int32_t *__restrict__ done)
+                   T sgn, T h, const int32_t *__restrict__ done, const T *__restrict__ dotw,
+                   double *__restrict__ dotpart)
 {
     static_assert(C % 4 == 0 && (!STRIDED || LPB == 4 || LPB == 2) && (!BLK || !STRIDED || LPB == 4),
                   "vector layout");
     if (done != nullptr && *done) return;
+    double dacc = 0.0;   // sum out * dotw over the written outputs (contiguous lines only)
+    __shared__ double dred[16];
     using V4 = typename vec4<T>::type;
     constexpr int W = STRIDED ? LPB : 4;   // vector width of the global accesses
     using VW = typename vecw<T, W>::type;
@@ -506,6 +509,10 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
                         V4 x;
                         x.x = u[4 * q]; x.y = u[4 * q + 1]; x.z = u[4 * q + 2]; x.w = u[4 * q + 3];
                         dst[q] = x;
+                        if (dotw != nullptr) {
+                            const V4 wv = *reinterpret_cast<const V4 *>(dotw + L * n + j0 + 4 * q);
+                            dacc += (double)x.x * wv.x + (double)x.y * wv.y + (double)x.z * wv.z + (double)x.w * wv.w;
+                        }
                     }
                 }
             }
@@ -528,6 +535,17 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
                 *reinterpret_cast<VW *>(dst + (long long)j * rs) = x;
             }
             __syncthreads();
+        }
+    }
+    if (dotw != nullptr) {   // uniform: one partial per workgroup, fixed order
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) dacc += __shfl_xor(dacc, o, kWave);
+        if ((tid & (kWave - 1)) == 0) dred[tid / kWave] = dacc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < nthr / kWave; ++w) sum += dred[w];
+            dotpart[blockIdx.x] = sum;
         }
     }
 }
@@ -610,7 +628,8 @@ static hipError_t allow_smem(KernelT fn, size_t smem, bool &done_flag)
 
 template <typename T, int C, int LPB, bool STRIDED, bool BLK>
 static hipError_t launch_pf(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads, T sgn,
-                            const int32_t *done, hipStream_t stream)
+                            const int32_t *done, hipStream_t stream, const T *dotw = nullptr,
+                            double *dotpart = nullptr, int *ndot = nullptr)
 {
     static bool attr = false;
     const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
@@ -621,7 +640,8 @@ static hipError_t launch_pf(const T *in, T *out, int n, int inner, long long nli
     long long blocks = resident_blocks((const void *)fn, threads, smem);
     if (blocks > groups) blocks = groups;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(threads), smem, stream, in, out, n, inner, nlines, tpl, sgn,
-                       T(1.0) / T(n), done);
+                       T(1.0) / T(n), done, dotw, dotpart);
+    if (ndot != nullptr) *ndot = dotw != nullptr ? (int)blocks : 0;
     return hipGetLastError();
 }
 
@@ -629,8 +649,10 @@ static hipError_t launch_pf(const T *in, T *out, int n, int inner, long long nli
 // layout of a 2D field (only with the persistent kernel).
 template <typename T, int C, int LPB>
 static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long long nlines, int tpl, int threads,
-                                 T sgn, const int32_t *done, hipStream_t stream, bool persistent, bool blk)
+                                 T sgn, const int32_t *done, hipStream_t stream, bool persistent, bool blk,
+                                 const T *dotw, double *dotpart, int *ndot)
 {
+    if (ndot != nullptr) *ndot = 0;
     const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
     const long long groups = (nlines + LPB - 1) / LPB;
     const T h = T(1.0) / T(n);
@@ -645,8 +667,10 @@ static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long lon
                 return launch_pf<T, C, 2, true, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream);
         }
         if (inner == 1)
-            return blk ? launch_pf<T, C, LPB, false, true>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream)
-                       : launch_pf<T, C, LPB, false, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream);
+            return blk ? launch_pf<T, C, LPB, false, true>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream,
+                                                           dotw, dotpart, ndot)
+                       : launch_pf<T, C, LPB, false, false>(in, out, n, inner, nlines, tpl, threads, sgn, done, stream,
+                                                            dotw, dotpart, ndot);
         return hipErrorInvalidValue;
     }
     if (blk) return hipErrorInvalidValue;
@@ -678,7 +702,8 @@ static bool ct_uses_persistent(int n, int inner, const void *in, const void *out
 
 template <typename T>
 static hipError_t launch_ct_axis_blk(const T *in, T *out, int n, int inner, long long nlines, T sgn,
-                                     const int32_t *done, hipStream_t stream, CtCfg cfg, bool blk)
+                                     const int32_t *done, hipStream_t stream, CtCfg cfg, bool blk,
+                                     const T *dotw = nullptr, double *dotpart = nullptr, int *ndot = nullptr)
 {
     const CtShape s = ct_shape(n, inner > 1, sizeof(T), cfg);
     if (s.tpl > 1024 || s.threads > ct_max_threads(s.C, s.lpb)) return hipErrorInvalidValue;
@@ -688,7 +713,8 @@ static hipError_t launch_ct_axis_blk(const T *in, T *out, int n, int inner, long
     if (blk && !pers) return hipErrorInvalidValue;
 #define BFM_CT_CASE(CC, LL)                                                                               \
     if (s.C == CC && s.lpb == LL)                                                                         \
-        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream, pers, blk);
+        return launch_ct_impl<T, CC, LL>(in, out, n, inner, nlines, s.tpl, s.threads, sgn, done, stream, pers, blk, \
+                                         dotw, dotpart, ndot);
     BFM_CT_CASE(16, 1) BFM_CT_CASE(16, 4) BFM_CT_CASE(8, 1) BFM_CT_CASE(8, 2) BFM_CT_CASE(8, 4)
     BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
     BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64) BFM_CT_CASE(4, 1)
@@ -712,15 +738,17 @@ hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nline
 // scratch, and the rows read it: both passes then write whole contiguous runs.
 template <typename T>
 hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
-                            const CtCfg *cfg, T *scratch)
+                            const CtCfg *cfg, T *scratch, const T *dotw, double *dotpart, int *ndot)
 {
+    if (ndot != nullptr) *ndot = 0;
     const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
     if (g.ndim == 2 && scratch != nullptr && scratch != in && scratch != out && (g.n[1] & 3) == 0 &&
         ct_uses_persistent<T>(g.n[0], g.n[1], in, scratch, c0) && ct_shape(g.n[0], true, sizeof(T), c0).lpb == 4 &&
         ct_uses_persistent<T>(g.n[1], 1, scratch, out, c1)) {
         hipError_t e = launch_ct_axis_blk<T>(in, scratch, g.n[0], g.n[1], g.n[1], T(-1), done, stream, c0, true);
         if (e != hipSuccess) return e;
-        return launch_ct_axis_blk<T>(scratch, out, g.n[1], 1, g.n[0], T(1), done, stream, c1, true);
+        return launch_ct_axis_blk<T>(scratch, out, g.n[1], 1, g.n[0], T(1), done, stream, c1, true, dotw, dotpart,
+                                     ndot);
     }
     for (int a = g.ndim - 1; a >= 0; --a) {
         const int n = g.n[a];
@@ -739,9 +767,9 @@ template hipError_t launch_ct_axis<float>(const float *, float *, int, int, long
 template hipError_t launch_ct_axis<double>(const double *, double *, int, int, long long, double,
                                            const int32_t *, hipStream_t, CtCfg);
 template hipError_t ctransform_field<float>(const Grid &, const float *, float *, const int32_t *, hipStream_t,
-                                            const CtCfg *, float *);
+                                            const CtCfg *, float *, const float *, double *, int *);
 template hipError_t ctransform_field<double>(const Grid &, const double *, double *, const int32_t *, hipStream_t,
-                                             const CtCfg *, double *);
+                                             const CtCfg *, double *, const double *, double *, int *);
 template size_t ct_smem_bytes<float>(int, int, int);
 template size_t ct_smem_bytes<double>(int, int, int);
 

@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(512)
 dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, DctArgs ax, int zero_b,
                  const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw, const T *__restrict__ lam0,
                  const T *__restrict__ lamA, const T *__restrict__ lamB, double *__restrict__ gpart,
-                 const int32_t *__restrict__ done)
+                 const T *__restrict__ dotw, const int32_t *__restrict__ done)
 {
     if (done != nullptr && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -577,13 +577,28 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
                     }
                     if (hasa) *reinterpret_cast<typename v4t<T>::type *>(out + ba + j4) = oa;
                     if (hasb) *reinterpret_cast<typename v4t<T>::type *>(out + bbb + j4) = ob;
+                    if (dotw != nullptr) {   // sum out * dotw of the written values
+                        const typename v4t<T>::type wa = *reinterpret_cast<const typename v4t<T>::type *>(dotw + ba + j4);
+                        gacc += (double)oa.x * wa.x + (double)oa.y * wa.y + (double)oa.z * wa.z + (double)oa.w * wa.w;
+                        if (hasb) {
+                            const typename v4t<T>::type wb =
+                                *reinterpret_cast<const typename v4t<T>::type *>(dotw + bbb + j4);
+                            gacc += (double)ob.x * wb.x + (double)ob.y * wb.y + (double)ob.z * wb.z + (double)ob.w * wb.w;
+                        }
+                    }
                 } else {
                     #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (j4 + e >= n) break;
                         const long long ia = ba + j4 + e, ib = bbb + j4 + e;
-                        if (hasa) out[ia] = base != nullptr ? base[ia] + sc * xa[e] : xa[e];
-                        if (hasb) out[ib] = base != nullptr ? base[ib] + sc * xb[e] : xb[e];
+                        if (hasa) {
+                            out[ia] = base != nullptr ? base[ia] + sc * xa[e] : xa[e];
+                            if (dotw != nullptr) gacc += (double)out[ia] * dotw[ia];
+                        }
+                        if (hasb) {
+                            out[ib] = base != nullptr ? base[ib] + sc * xb[e] : xb[e];
+                            if (dotw != nullptr) gacc += (double)out[ib] * dotw[ib];
+                        }
                     }
                 }
             }
@@ -621,7 +636,7 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
             }
         }
     }
-    if (MODE == DM_FUSED) {
+    if (MODE == DM_FUSED || (MODE == DM_INV && CONTIG && dotw != nullptr)) {   // uniform
         const double gs = block_sum_any(gacc, red);
         if (threadIdx.x == 0) gpart[blockIdx.x] = gs;
     }
@@ -636,7 +651,8 @@ static int dct_block(int n) {
 template <typename T, int NPAIR, int MODE, bool CONTIG>
 static hipError_t launch_dct_impl(const T *a, T *b, T *out, const T *base, const double *scale, const DctArgs &ax,
                                   int zero_b, const void *tw, const void *qw, const T *lam0, const T *lamA,
-                                  const T *lamB, double *gpart, const int32_t *done, hipStream_t stream)
+                                  const T *lamB, double *gpart, const int32_t *done, hipStream_t stream,
+                                  const T *dotw = nullptr)
 {
     const int bd = dct_block(ax.n);
     if (bd * NPAIR > 512) return hipErrorInvalidValue;
@@ -653,7 +669,7 @@ static hipError_t launch_dct_impl(const T *a, T *b, T *out, const T *base, const
     }
     hipLaunchKernelGGL((dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>), dim3((unsigned)blocks), dim3(bd * NPAIR),
                        smem, stream, a, b, out, base, scale, ax, zero_b, (const cpx<T> *)tw, (const cpx<T> *)qw,
-                       lam0, lamA, lamB, gpart, done);
+                       lam0, lamA, lamB, gpart, dotw, done);
     return hipGetLastError();
 }
 
@@ -693,12 +709,14 @@ hipError_t launch_dct_fwd(const T *a, T *b, T *out, const AxisPlan &ap, long lon
 
 template <typename T>
 hipError_t launch_dct_inv(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap, long long N,
-                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream)
+                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream, const T *dotw,
+                          double *dotpart)
 {
     const DctArgs ax = make_args(ap, N);
     if (ap.inner == 1)
         return launch_dct_impl<T, 1, DM_INV, true>(in, nullptr, out, base, scale, ax, 0, tw, qw, nullptr, nullptr,
-                                                   nullptr, nullptr, done, stream);
+                                                   nullptr, dotpart, done, stream, dotw);
+    if (dotw != nullptr) return hipErrorInvalidValue;   // the sum is fused into contiguous passes only
     if (dct_two_pairs<T>(ap.n))
         return launch_dct_impl<T, 2, DM_INV, false>(in, nullptr, out, base, scale, ax, 0, tw, qw, nullptr, nullptr,
                                                     nullptr, nullptr, done, stream);
@@ -739,7 +757,7 @@ long long dct_fused_parts(int n0, long long N, size_t esz)
                                           const void *, const int32_t *, hipStream_t);                         \
     template hipError_t launch_dct_inv<T>(const T *, T *, const T *, const double *, const AxisPlan &,        \
                                           long long, const void *, const void *, const int32_t *,             \
-                                          hipStream_t);                                                       \
+                                          hipStream_t, const T *, double *);                                                       \
     template hipError_t launch_dct_fused<T>(T *, const AxisPlan &, long long, int, int, const void *,         \
                                             const void *, const T *, const T *, const T *, double *, int *,    \
                                             const int32_t *, hipStream_t);

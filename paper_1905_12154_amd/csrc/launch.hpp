@@ -23,9 +23,14 @@ struct CtCfg {
     int lpb = 0;
     int pers = 0;
 };
+// With `scratch`, 2D fields may take the column-blocked two-pass form; when
+// it does and dotw is given, its second pass also writes one float64 partial
+// per workgroup of sum out * dotw into dotpart and sets *ndot to their count
+// (otherwise *ndot = 0).
 template <typename T>
 hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *done, hipStream_t stream,
-                            const CtCfg *cfg = nullptr, T *scratch = nullptr);
+                            const CtCfg *cfg = nullptr, T *scratch = nullptr, const T *dotw = nullptr,
+                            double *dotpart = nullptr, int *ndot = nullptr);
 template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
                           const int32_t *done, hipStream_t stream, CtCfg cfg = CtCfg{});
@@ -37,8 +42,11 @@ template <typename T>
 hipError_t launch_dct_fwd(const T *a, T *b, T *out, const AxisPlan &ap, long long N, int zero_b, const void *tw,
                           const void *qw, const int32_t *done, hipStream_t stream);
 template <typename T>
+// dotw (contiguous axis only): also one float64 partial per workgroup of
+// sum out * dotw into dotpart[workgroup] ((lines + 1) / 2 workgroups).
 hipError_t launch_dct_inv(const T *in, T *out, const T *base, const double *scale, const AxisPlan &ap, long long N,
-                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream);
+                          const void *tw, const void *qw, const int32_t *done, hipStream_t stream,
+                          const T *dotw = nullptr, double *dotpart = nullptr);
 template <typename T>
 hipError_t launch_dct_fused(T *X, const AxisPlan &ap0, long long N, int nA, int nB, const void *tw, const void *qw,
                             const T *lam0, const T *lamA, const T *lamB, double *gpart, int *nparts,
@@ -82,6 +90,7 @@ struct CtrlParams {
     int nred;             // partials of the grid-stride kernels (dot products, statistics)
     int nsplat;           // partials of the deposition kernel (S_PRIMAL, S_PC_SRC)
     int ngpart;           // partials of G (separate array)
+    int nqt, nqs;         // partials in S_Q_TGT and S_Q_SRC (fused sums or the dot kernel's)
 };
 
 hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,

@@ -271,8 +271,8 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
         return;
     }
     if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
-        const double a = slot_reduce_sum(partials, sl, S_Q_TGT, nb, sh);
-        const double b = slot_reduce_sum(partials, sl, S_Q_SRC, nb, sh);
+        const double a = slot_reduce_sum(partials, sl, S_Q_TGT, prm.nqt, sh);
+        const double b = slot_reduce_sum(partials, sl, S_Q_SRC, prm.nqs, sh);
         if (threadIdx.x == 0) {
             st->q_src = b;
             st->J_new = prm.vol * (a + b);

@@ -206,7 +206,10 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     P->off_state = off;  off = align256(off + sizeof(DevState));
     P->off_trace = off;  off = align256(off + sizeof(TraceRec) * kMaxTrace);
     P->nsplat = (int)splat_blocks(g);
-    P->slot_len = P->nsplat > kMaxRedBlocks ? P->nsplat : kMaxRedBlocks;
+    // slots hold up to max(deposition workgroups, 4096) partials: the grid-stride
+    // reductions (1024), and the sums fused into the last inverse DCT pass and
+    // the c-transform's second pass when their grids fit
+    P->slot_len = P->nsplat > 4096 ? P->nsplat : 4096;
     P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * (size_t)P->slot_len);
     P->gparts = (int)dct_fused_parts(g.n[0], g.N, P->esz);
     P->off_gpart = off;  off = align256(off + sizeof(double) * (size_t)P->gparts);
@@ -282,6 +285,7 @@ static CtrlParams ctrl_params(bfm_plan P)
     c.nred = P->red_blocks;
     c.nsplat = P->nsplat;
     c.ngpart = P->gparts;
+    c.nqt = c.nqs = P->red_blocks;
     return c;
 }
 
@@ -327,21 +331,30 @@ static hipError_t poisson_forward(bfm_plan P, const Ws &w, const T *a, T *b, int
     return e;
 }
 
+// dotw (with update): the last pass also sums update * dotw into dotpart
+// when its grid fits a slot; *ndot = partial count, or 0 when not fused.
 template <typename T>
 static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *update, const int32_t *done,
-                                  hipStream_t s)
+                                  hipStream_t s, const T *dotw = nullptr, double *dotpart = nullptr,
+                                  int *ndot = nullptr)
 {
     const Grid &g = P->g;
     const int d = g.ndim;
     hipError_t e;
+    if (ndot != nullptr) *ndot = 0;
     if (d == 3) {
         e = launch_dct_inv<T>(F, F, nullptr, nullptr, P->ax[1], g.N, w.tables + P->tab_tw[1], w.tables + P->tab_qw[1],
                               done, s);
         if (e != hipSuccess) return e;
     }
     T *dst = update != nullptr ? update : out;
-    return launch_dct_inv<T>(F, dst, update, update != nullptr ? &w.st->sigma : nullptr, P->ax[d - 1], g.N,
-                             w.tables + P->tab_tw[d - 1], w.tables + P->tab_qw[d - 1], done, s);
+    const long long nblk = (g.N / g.n[d - 1] + 1) / 2;   // workgroups of the contiguous inverse pass
+    const bool fuse = dotw != nullptr && update != nullptr && ndot != nullptr && nblk <= P->slot_len;
+    e = launch_dct_inv<T>(F, dst, update, update != nullptr ? &w.st->sigma : nullptr, P->ax[d - 1], g.N,
+                          w.tables + P->tab_tw[d - 1], w.tables + P->tab_qw[d - 1], done, s,
+                          fuse ? dotw : nullptr, fuse ? dotpart : nullptr);
+    if (e == hipSuccess && fuse) *ndot = (int)nblk;
+    return e;
 }
 
 // One half-step of Algorithm 1 on J(p) = <p, tgt> + <p^c, src>:
@@ -370,11 +383,28 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
         hipSuccess)
         return e;
     if (head_only) return hipSuccess;
-    if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s)) != hipSuccess) return e;
-    if ((e = ctransform_field<T>(g, p, q, done, s, P->ct_cfg, F)) != hipSuccess) return e;   // F consumed above
-    if ((e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s)) != hipSuccess)
+    // the two sums of J at the stepped potential, <p, tgt> and <q, src>,
+    // fused into the passes that write p and q where possible
+    int nqt = 0, nqs = 0;
+    const bool al = ((((uintptr_t)tgt) | ((uintptr_t)src)) & 15) == 0;   // the fused passes read 16-byte vectors
+    if ((e = poisson_inverse<T>(P, w, F, nullptr, p, done, s, al ? tgt : nullptr, w.slot(S_Q_TGT), &nqt)) !=
+        hipSuccess)
         return e;
-    return launch_ctrl(w.st, w.part, w.gpart, step_mode, cp, w.trace, s);
+    if ((e = ctransform_field<T>(g, p, q, done, s, P->ct_cfg, F, al ? src : nullptr, w.slot(S_Q_SRC), &nqs)) !=
+        hipSuccess)
+        return e;   // F consumed above
+    if (nqs > w.slot_len) return hipErrorInvalidValue;
+    if (nqt == 0 && nqs == 0)
+        e = launch_dot2<T>(p, tgt, q, src, g.N, w.slot(S_Q_TGT), w.slot(S_Q_SRC), nb, done, s);
+    else if (nqt == 0)
+        e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_Q_TGT), nullptr, nb, done, s);
+    else if (nqs == 0)
+        e = launch_dot2<T>(q, src, nullptr, nullptr, g.N, w.slot(S_Q_SRC), nullptr, nb, done, s);
+    if (e != hipSuccess) return e;
+    CtrlParams cs = cp;
+    cs.nqt = nqt > 0 ? nqt : nb;
+    cs.nqs = nqs > 0 ? nqs : nb;
+    return launch_ctrl(w.st, w.part, w.gpart, step_mode, cs, w.trace, s);
 }
 
 // Solve in four parts so that the iterations can be enqueued without any host
