@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-pts×iters/s & time to dual gap<1e-4 at 4096²; batched+grad vs plain"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20     # calibration copy: reads and writes this many bytes
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ct_axis0_c3_4096_f32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ct_rows_blocked_sum_c3_4096_f32_traffic.json")
 # sources that decide the c-transform kernel's code: counters taken on
 # another version of them no longer describe the kernel
 TRAFFIC_SOURCES = ["paper_1905_12154_amd/csrc/ctransform.hip", "paper_1905_12154_amd/csrc/common.hpp",
@@ -42,7 +42,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, tuning_axis):
+def measured_traffic(kernel, tuning):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     runs (FETCH_SIZE and WRITE_SIZE, each scaled by the counter's reading on
     a copy of known size), or None when the kernel's sources or launch shape
@@ -54,7 +54,7 @@ def measured_traffic(kernel, tuning_axis):
         return None
     if t.get("kernel") != kernel or t.get("source_sha256") != kernel_source_hash():
         return None
-    if tuning_axis is not None and list(t.get("launch_shape", [])) != list(tuning_axis):
+    if tuning is not None and [list(x) for x in t.get("launch_shape", [])] != [list(x) for x in tuning]:
         return None
     return t["hbm_bytes_per_launch"]
 
@@ -80,16 +80,18 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_times(plan, phi, reps):
+def kernel_times(plan, phi, reps, weight=None):
     """Average duration (ms) of each hot kernel class, HIP events on the
     stream the library launches on (the current PyTorch stream).  Inputs are
     what the solver feeds these kernels: the current potential for the first
-    c-transform pass, that pass's output for the second."""
+    c-transform pass, that pass's output for the second.  When the solver
+    runs the column-blocked two-pass transform (2D, persistent shapes), its
+    two passes are timed as launched there: the column pass, and the row
+    pass with the fused sum against `weight` (as in a gradient step)."""
     import torch
+    from paper_1905_12154_amd import bfm
     s = torch.cuda.current_stream()
     f = phi.contiguous()
-    a1 = plan.ctransform_axis(f, 1, -1)
-    out = torch.empty_like(f)
     res = {}
 
     def timeit(fn):
@@ -102,9 +104,37 @@ def kernel_times(plan, phi, reps):
         b.synchronize()
         return a.elapsed_time(b) / reps
 
+    try:
+        mid = plan.ctransform_pass(f, 0)
+        out = torch.empty_like(f)
+        res["ct_cols_blocked"] = timeit(lambda: plan.ctransform_pass(f, 0, out=mid))
+        res["ct_rows_blocked"] = timeit(lambda: plan.ctransform_pass(mid, 1, out=out))
+        if weight is not None:
+            res["ct_rows_blocked_sum"] = timeit(lambda: plan.ctransform_pass(mid, 1, out=out, weight=weight))
+    except bfm.BFMError:
+        pass
+    a1 = plan.ctransform_axis(f, 1, -1)
+    out = torch.empty_like(f)
     res["ct_axis1"] = timeit(lambda: plan.ctransform_axis(f, 1, -1, out=out))
     res["ct_axis0"] = timeit(lambda: plan.ctransform_axis(a1, 0, 1, out=out))
     return res
+
+
+def dominant_kernel(kt, N, esz=4):
+    """The kernel with the largest time per iteration (4 c-transforms) and its
+    algorithmic bytes per launch: a pass reads its input and writes its
+    output (2 words per point); the row pass with the fused sum also reads
+    the weight field (3 words)."""
+    if "ct_cols_blocked" in kt:
+        rows = kt.get("ct_rows_blocked_sum", kt["ct_rows_blocked"])
+        per_iter = {"ct_cols_blocked": 4 * kt["ct_cols_blocked"],
+                    "ct_rows_blocked_sum" if "ct_rows_blocked_sum" in kt else "ct_rows_blocked":
+                        2 * kt["ct_rows_blocked"] + 2 * rows}
+    else:
+        per_iter = {"ct_axis1": 4 * kt["ct_axis1"], "ct_axis0": 4 * kt["ct_axis0"]}
+    dom = max(per_iter, key=per_iter.get)
+    words = 3 if dom == "ct_rows_blocked_sum" else 2
+    return dom, words * N * esz
 
 
 def batched_leg(iters, tol):
@@ -230,7 +260,7 @@ def pmc_leg(n, args):
     rw = warm.solve(mu, nu, return_map=False)
     plan = bfm.Plan((n, n), torch.float32)
     tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
-    kt = kernel_times(plan, rw.phi, args.kernel_reps)
+    kt = kernel_times(plan, rw.phi, args.kernel_reps, weight=mu)
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -285,12 +315,10 @@ def main():
     min_gap = min(e["gap"] for e in tr) if tr else float("nan")
 
     # dominant kernel: per-iteration time = launches per iteration x duration
-    kt = kernel_times(plan, r.phi, args.kernel_reps)
-    per_iter = {"ct_axis1": 4 * kt["ct_axis1"], "ct_axis0": 4 * kt["ct_axis0"]}
-    dom = max(per_iter, key=per_iter.get)
-    bytes_per_launch = 2 * N * 4          # read u, write the transformed line (float32)
+    kt = kernel_times(plan, r.phi, args.kernel_reps, weight=mu)
+    dom, bytes_per_launch = dominant_kernel(kt, N)
     achieved = bytes_per_launch / (kt[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, tuning[0 if dom == "ct_axis0" else 1] if tuning else None)
+    traffic = measured_traffic(dom, tuning)
 
     out = {
         "metric": METRIC,

@@ -202,6 +202,27 @@ bfm_status bfm_grad(bfm_plan plan, const void *phi, const void *psi, double scal
 bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t sign, const void *in, void *out,
                                void *stream);
 
+/* Primitive: one pass of the two-pass form of a 2D c-transform that the
+ * solver uses when it applies (Section 4.1, separable evaluation; the axes
+ * are independent minimisations, so columns may go first):
+ *   pass 0: out = the column pass of u = -in, written in the column-blocked
+ *           layout: element (r, c) of the n0 x n1 result at
+ *           (c / 4) * 4 n0 + 4 r + c % 4 (each group of four columns is one
+ *           contiguous run);
+ *   pass 1: in = a column-blocked field, out = its row pass, row-major, so
+ *           pass 1 after pass 0 gives in^c.  With `weight` (a row-major
+ *           field), also sum_x out(x) weight(x) in float64: its per-workgroup
+ *           partials go to the workspace and, when host_sum is non-NULL, the
+ *           fixed-order total to *host_sum (synchronises `stream`).
+ * in, out (and weight) are distinct device fields of N elements, 16-byte
+ * aligned.  BFM_EINVAL for a NULL or aliased field, pass not 0 or 1, or
+ * host_sum without pass 1 and a weight.  BFM_EUNSUPPORTED when the form does
+ * not apply: not 2D, n1 not a multiple of 4, or launch shapes that are not
+ * persistent with four-column groups (the float32 default for large enough
+ * grids; float64 plans need bfm_plan_set_tuning). */
+bfm_status bfm_ctransform_pass(bfm_plan plan, int32_t pass, const void *in, void *out, const void *weight,
+                               double *host_sum, void *workspace, size_t ws_bytes, void *stream);
+
 /* Copy the per-iteration trace of the last bfm_solve run on `workspace`
  * to host memory: record r is 8 doubles (iteration, dual J(phi_n), primal
  * P_n, G_n, gap_n, sigma_n, J(phi_{n+1/2}), I(psi_{n+1})) taken at the head of

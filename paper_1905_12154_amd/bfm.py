@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
-            "bfm_plan_tuning", "bfm_plan_set_tuning"]
+            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass"]
 
 
 class BFMError(RuntimeError):
@@ -79,6 +79,7 @@ def lib():
         L.bfm_autotune.argtypes = [vp, vp, vp, sz, vp]
         L.bfm_plan_tuning.argtypes = [vp, P(i32)]
         L.bfm_plan_set_tuning.argtypes = [vp, P(i32)]
+        L.bfm_ctransform_pass.argtypes = [vp, i32, vp, vp, vp, P(ctypes.c_double), vp, sz, vp]
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
                                         P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
@@ -212,6 +213,21 @@ class Plan:
             for k in range(3):
                 flat[3 * a + k] = int(tri[k])
         _check(lib().bfm_plan_set_tuning(self._h, flat))
+
+    def ctransform_pass(self, f, pass_: int, out=None, weight=None, want_sum: bool = False):
+        """One pass of the column-blocked 2D transform (``bfm_ctransform_pass``):
+        pass 0 maps a row-major field to the column-blocked column pass of -f,
+        pass 1 a column-blocked field to the row-major transform; with
+        ``weight`` and ``want_sum`` also returns sum(out * weight)."""
+        f = self._field(f, "f")
+        out = torch.empty_like(f) if out is None else out
+        w = None if weight is None else self._field(weight, "weight")
+        ws = self.workspace(f.device)
+        total = ctypes.c_double()
+        _check(lib().bfm_ctransform_pass(self._h, int(pass_), _ptr(f), _ptr(out), _ptr(w),
+                                         ctypes.byref(total) if want_sum else None, _ptr(ws), self.ws_bytes,
+                                         _stream(f.device)))
+        return (out, total.value) if want_sum else out
 
     def ctransform_axis(self, f, axis: int, sign: int = -1, out=None):
         f = self._field(f, "f")

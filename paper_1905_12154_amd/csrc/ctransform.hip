@@ -730,6 +730,31 @@ hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nline
     return launch_ct_axis_blk<T>(in, out, n, inner, nlines, sgn, done, stream, cfg, false);
 }
 
+// The column-blocked two-pass form of a 2D transform applies when both
+// passes run the persistent kernel (four-column groups on the columns) with
+// 16-byte aligned fields and a row length divisible by 4.
+template <typename T>
+bool ct_blocked_applies(const Grid &g, const void *in, const void *mid, const void *out, const CtCfg *cfg)
+{
+    const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
+    return g.ndim == 2 && (g.n[1] & 3) == 0 && ct_uses_persistent<T>(g.n[0], g.n[1], in, mid, c0) &&
+           ct_shape(g.n[0], true, sizeof(T), c0).lpb == 4 && ct_uses_persistent<T>(g.n[1], 1, mid, out, c1);
+}
+
+// One pass of that form: pass 0 transforms the columns of u = -in and
+// writes the column-blocked layout; pass 1 transforms the rows of a
+// column-blocked field and writes row-major output (with dotw, also the
+// per-workgroup partials of sum out * dotw).
+template <typename T>
+hipError_t ct_blocked_pass(const Grid &g, int pass, const T *in, T *out, const int32_t *done, hipStream_t stream,
+                           const CtCfg *cfg, const T *dotw, double *dotpart, int *ndot)
+{
+    const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
+    if (ndot != nullptr) *ndot = 0;
+    if (pass == 0) return launch_ct_axis_blk<T>(in, out, g.n[0], g.n[1], g.n[1], T(-1), done, stream, c0, true);
+    return launch_ct_axis_blk<T>(in, out, g.n[1], 1, g.n[0], T(1), done, stream, c1, true, dotw, dotpart, ndot);
+}
+
 // Full c-transform of a field: out = in^c.  The axes are independent
 // minimisations, so any order gives the same minimum.  Default order: axis
 // ndim-1 first (u = -in), then each earlier axis on the running result.  In
@@ -741,14 +766,10 @@ hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *d
                             const CtCfg *cfg, T *scratch, const T *dotw, double *dotpart, int *ndot)
 {
     if (ndot != nullptr) *ndot = 0;
-    const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
-    if (g.ndim == 2 && scratch != nullptr && scratch != in && scratch != out && (g.n[1] & 3) == 0 &&
-        ct_uses_persistent<T>(g.n[0], g.n[1], in, scratch, c0) && ct_shape(g.n[0], true, sizeof(T), c0).lpb == 4 &&
-        ct_uses_persistent<T>(g.n[1], 1, scratch, out, c1)) {
-        hipError_t e = launch_ct_axis_blk<T>(in, scratch, g.n[0], g.n[1], g.n[1], T(-1), done, stream, c0, true);
+    if (scratch != nullptr && scratch != in && scratch != out && ct_blocked_applies<T>(g, in, scratch, out, cfg)) {
+        hipError_t e = ct_blocked_pass<T>(g, 0, in, scratch, done, stream, cfg);
         if (e != hipSuccess) return e;
-        return launch_ct_axis_blk<T>(scratch, out, g.n[1], 1, g.n[0], T(1), done, stream, c1, true, dotw, dotpart,
-                                     ndot);
+        return ct_blocked_pass<T>(g, 1, scratch, out, done, stream, cfg, dotw, dotpart, ndot);
     }
     for (int a = g.ndim - 1; a >= 0; --a) {
         const int n = g.n[a];
@@ -770,6 +791,12 @@ template hipError_t ctransform_field<float>(const Grid &, const float *, float *
                                             const CtCfg *, float *, const float *, double *, int *);
 template hipError_t ctransform_field<double>(const Grid &, const double *, double *, const int32_t *, hipStream_t,
                                              const CtCfg *, double *, const double *, double *, int *);
+template bool ct_blocked_applies<float>(const Grid &, const void *, const void *, const void *, const CtCfg *);
+template bool ct_blocked_applies<double>(const Grid &, const void *, const void *, const void *, const CtCfg *);
+template hipError_t ct_blocked_pass<float>(const Grid &, int, const float *, float *, const int32_t *, hipStream_t,
+                                           const CtCfg *, const float *, double *, int *);
+template hipError_t ct_blocked_pass<double>(const Grid &, int, const double *, double *, const int32_t *,
+                                            hipStream_t, const CtCfg *, const double *, double *, int *);
 template size_t ct_smem_bytes<float>(int, int, int);
 template size_t ct_smem_bytes<double>(int, int, int);
 

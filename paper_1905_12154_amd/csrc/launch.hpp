@@ -23,6 +23,11 @@ struct CtCfg {
     int lpb = 0;
     int pers = 0;
 };
+template <typename T>
+bool ct_blocked_applies(const Grid &g, const void *in, const void *mid, const void *out, const CtCfg *cfg);
+template <typename T>
+hipError_t ct_blocked_pass(const Grid &g, int pass, const T *in, T *out, const int32_t *done, hipStream_t stream,
+                           const CtCfg *cfg, const T *dotw = nullptr, double *dotpart = nullptr, int *ndot = nullptr);
 // With `scratch`, 2D fields may take the column-blocked two-pass form; when
 // it does and dotw is given, its second pass also writes one float64 partial
 // per workgroup of sum out * dotw into dotpart and sets *ndot to their count

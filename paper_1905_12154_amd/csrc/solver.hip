@@ -937,6 +937,50 @@ extern "C" bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t s
     return BFM_OK;
 }
 
+template <typename T>
+static bfm_status ct_pass_impl(bfm_plan plan, int pass, const T *in, T *out, const T *weight, double *host_sum,
+                               const Ws &w, hipStream_t s)
+{
+    const Grid &g = plan->g;
+    const bool ok = pass == 0 ? ct_blocked_applies<T>(g, in, out, out, plan->ct_cfg)
+                              : ct_blocked_applies<T>(g, in, in, out, plan->ct_cfg);
+    if (!ok)
+        return fail(BFM_EUNSUPPORTED, "the column-blocked two-pass transform does not apply to this plan "
+                                      "(2D, last size a multiple of 4, persistent launch shapes, 16-byte aligned "
+                                      "fields)");
+    int nd = 0;
+    HIP_TRY(ct_blocked_pass<T>(g, pass, in, out, nullptr, s, plan->ct_cfg, pass == 1 ? weight : nullptr,
+                               w.slot(S_Q_SRC), &nd));
+    if (nd > w.slot_len) return fail(BFM_EDEVICE, "c-transform pass: %d partials exceed the slot", nd);
+    if (host_sum != nullptr) {
+        std::vector<double> h(nd > 0 ? nd : 1);
+        if (nd > 0) HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_Q_SRC), nd * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double sum = 0.0;
+        for (int i = 0; i < nd; ++i) sum += h[i];
+        *host_sum = sum;
+    }
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_ctransform_pass(bfm_plan plan, int32_t pass, const void *in, void *out, const void *weight,
+                                          double *host_sum, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || in == nullptr || out == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    if (pass != 0 && pass != 1) return fail(BFM_EINVAL, "pass must be 0 or 1");
+    if (in == out) return fail(BFM_EINVAL, "in and out must be distinct buffers");
+    if (host_sum != nullptr && (pass != 1 || weight == nullptr))
+        return fail(BFM_EINVAL, "host_sum needs pass 1 and a weight field");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return ct_pass_impl<double>(plan, pass, (const double *)in, (double *)out, (const double *)weight, host_sum,
+                                    w, s);
+    return ct_pass_impl<float>(plan, pass, (const float *)in, (float *)out, (const float *)weight, host_sum, w, s);
+}
+
 extern "C" bfm_status bfm_trace(bfm_plan plan, const void *workspace, size_t ws_bytes, double *host,
                                 int32_t max_records, int32_t *count, void *stream)
 {

@@ -132,6 +132,61 @@ def test_set_tuning_rejects_bad_values():
     assert plan.tuning() == [(0, 0, 0), (0, 0, 0)]
 
 
+def _blocked(x):
+    """Column-blocked layout of a 2D array: element (r, c) at (c // 4) 4 R + 4 r + c % 4."""
+    R, K = x.shape
+    return np.ascontiguousarray(x.reshape(R, K // 4, 4).transpose(1, 0, 2)).reshape(R, K)
+
+
+@pytest.mark.parametrize("shape,dtype,tuning", [((256, 512), torch.float32, None),
+                                                ((4096, 16), torch.float32, None),
+                                                ((96, 36), torch.float32, [(8, 4, 2), (16, 0, 2)]),
+                                                ((128, 64), torch.float64, [(8, 4, 2), (8, 0, 2)])])
+def test_ctransform_blocked_passes(shape, dtype, tuning):
+    """The two passes of the column-blocked 2D transform: pass 0 is the
+    column pass of -f in the blocked layout, pass 1 the row pass back to
+    row-major; with a weight, pass 1 also returns sum(out * weight)."""
+    f = rand_field(shape, 4, "potential")
+    if dtype == torch.float32:
+        f = f.astype(np.float32).astype(np.float64)
+    plan = bfm.Plan(shape, dtype)
+    if tuning is not None:
+        plan.set_tuning(tuning)
+    tol = (1e-13 if dtype == torch.float64 else 300 * np.finfo(np.float32).eps)
+    mid = plan.ctransform_pass(cuda(f, dtype), 0)
+    ref_mid = _blocked(ob.line_min(-f, 0))
+    assert np.max(np.abs(host(mid) - ref_mid)) <= tol * max(1.0, np.max(np.abs(ref_mid)))
+    w = np.random.default_rng(5).uniform(0.0, 2.0, size=shape)
+    out, total = plan.ctransform_pass(mid, 1, weight=cuda(w, dtype), want_sum=True)
+    ref = ob.ctransform(f)
+    assert np.max(np.abs(host(out) - ref)) <= tol * max(1.0, np.max(np.abs(ref)))
+    exact = float(np.sum(host(out) * host(cuda(w, dtype))))
+    assert abs(total - exact) <= 1e-12 * np.sum(np.abs(host(out)) * w) + 1e-300
+    assert np.array_equal(host(plan.ctransform_pass(mid, 1)), host(out))   # same kernel without the sum
+
+
+def test_ctransform_pass_errors():
+    f64 = bfm.Plan((64, 64), torch.float64)          # default float64 shapes are not persistent
+    x = cuda(np.zeros((64, 64)))
+    with pytest.raises(bfm.BFMError) as e:
+        f64.ctransform_pass(x, 0)
+    assert e.value.status == bfm.BFM_EUNSUPPORTED
+    odd = bfm.Plan((64, 54), torch.float32)           # rows not a multiple of 4
+    with pytest.raises(bfm.BFMError) as e:
+        odd.ctransform_pass(cuda(np.zeros((64, 54)), torch.float32), 0)
+    assert e.value.status == bfm.BFM_EUNSUPPORTED
+    p3 = bfm.Plan((16, 16, 16), torch.float32)
+    with pytest.raises(bfm.BFMError) as e:
+        p3.ctransform_pass(cuda(np.zeros((16, 16, 16)), torch.float32), 0)
+    assert e.value.status == bfm.BFM_EUNSUPPORTED
+    ok = bfm.Plan((64, 64), torch.float32)
+    y = cuda(np.zeros((64, 64)), torch.float32)
+    for bad in (lambda: ok.ctransform_pass(y, 2), lambda: ok.ctransform_pass(y, 0, out=y)):
+        with pytest.raises(bfm.BFMError) as e:
+            bad()
+        assert e.value.status == bfm.BFM_EINVAL
+
+
 def test_ctransform_in_place_and_linear_closed_form():
     shape = (96, 128)
     xs = ob.centres(shape)
