@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--c5-tol", type=float, default=1e-4)
     ap.add_argument("--c4-iters", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
+                         "separated by ';' (the shapes the bench's own run reported)")
     ap.add_argument("--pmc-leg", action="store_true",
                     help="only the dominant kernel's timing leg plus a %d MiB copy for counter calibration "
                          "(the program run under rocprofv3 --pmc)" % (COPY_BYTES >> 20))
@@ -259,7 +262,11 @@ def pmc_leg(n, args):
     warm = bfm.Plan((n, n), torch.float32, max_iters=max(args.warmup, 0), check_every=max(args.warmup, 1))
     rw = warm.solve(mu, nu, return_map=False)
     plan = bfm.Plan((n, n), torch.float32)
-    tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
+    if args.tuning:   # counters slow kernels unevenly: tuning under them would pick other shapes
+        plan.set_tuning([tuple(int(x) for x in ax.split(",")) for ax in args.tuning.split(";")])
+        tuning = plan.tuning()
+    else:
+        tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
     kt = kernel_times(plan, rw.phi, args.kernel_reps, weight=mu)
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
