@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--c5-tol", type=float, default=1e-4)
     ap.add_argument("--c4-iters", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-interp", action="store_true", help="skip the 1024^2 displacement-interpolation leg")
+    ap.add_argument("--interp-frames", type=int, default=11)
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
@@ -206,6 +208,36 @@ def c4_leg(iters, autotune):
     return {"workload": "c4: 3D 384^3, 6-Gaussian mixtures, float32", "iters": r.iters, "seconds": dt,
             "ms_per_iter": dt / max(r.iters, 1) * 1e3, "pts_iters_per_s": N * r.iters / dt, "gap": r.gap,
             "dual": r.dual, "tuning": plan.tuning()}
+
+
+def interp_leg(iters, tol, nframes):
+    """Displacement interpolation at 1024^2 (c2: ellipses to a 4-Gaussian
+    mixture, float32): solve to dual gap < tol (at most `iters` iterations),
+    then `nframes` interpolants rho_t = S_t # mu at evenly spaced t."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c2()
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    plan = bfm.Plan(mu.shape, torch.float32, max_iters=iters, tol=tol, check_every=4)
+    times = [k / (nframes - 1) for k in range(nframes)]
+    plan.solve(mu, nu, return_map=False)                 # warm-up
+    plan.interpolate(plan.solve(mu, nu, return_map=False).phi, mu, times[:2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = plan.solve(mu, nu, return_map=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    frames = plan.interpolate(r.phi, mu, times)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mass = float(mu.double().sum())
+    return {"workload": "c2: 1024^2, 5 ellipses to a 4-Gaussian mixture, float32", "tol": tol,
+            "iters": r.iters, "converged": bool(r.converged), "gap": r.gap, "solve_seconds": t1 - t0,
+            "frames": nframes, "frames_seconds": t2 - t1, "ms_per_frame": (t2 - t1) / nframes * 1e3,
+            "total_seconds": t2 - t0,
+            "max_frame_mass_error": max(abs(float(f.double().sum()) - mass) / mass for f in frames)}
 
 
 def cpu_baseline(n):
@@ -359,6 +391,8 @@ def main():
         out["batched_c5"] = batched_leg(args.c5_iters, args.c5_tol)
     if not args.no_c4:
         out["c4_3d"] = c4_leg(args.c4_iters, not args.no_autotune)
+    if not args.no_interp:
+        out["interp_c2"] = interp_leg(2000, 1e-5, max(2, args.interp_frames))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

@@ -157,6 +157,19 @@ bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg9);
  * later calls fail with BFM_EDEVICE. */
 bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9);
 
+/* Displacement interpolation (Section 4.3, optimal transport of images):
+ * for each time t_k in [0, 1],
+ *   rho_k = S_t # mu,  S_t(x) = t T(x) + (1 - t) x,  T(x) = x - grad phi^c(x),
+ * with the map and the multilinear deposition of bfm_pushforward (t = 0
+ * gives mu, t = 1 the pushforward by T).  phi is a potential from bfm_solve
+ * (T is then the computed map from mu to nu); phi and mu are device fields of
+ * N elements; rho is a device array of ntimes * N elements (frame k at
+ * offset k * N), written whole.  times is a host array of ntimes values.
+ * BFM_EINVAL for NULL arguments, ntimes < 1, a time outside [0, 1] or rho
+ * aliasing phi or mu.  Overwrites the workspace. */
+bfm_status bfm_interpolate(bfm_plan plan, const void *phi, const void *mu, int32_t ntimes, const double *times,
+                           void *rho, void *workspace, size_t ws_bytes, void *stream);
+
 /* Primitive: quadratic-cost c-transform on the grid (Definition of the
  * c-transform; separable evaluation of Section 4.1; per line the Legendre
  * transform on the lower convex hull, eq. legendre / legendre_search):

@@ -20,6 +20,11 @@ Pins (see tests/test_oracle_*.py):
                         against the exact discrete LP (HiGHS) on tiny grids,
                         the unconditional c-transform half of the monotone
                         chain, Gaussian-to-Gaussian affine maps.
+  * displacement_interpolant -- t = 0 gives the density itself, t = 1 the
+                        method's pushforward, whole-cell translations move by
+                        t times the shift, mass is conserved, and the
+                        interpolant of two Gaussians is the Gaussian with
+                        interpolated mean and standard deviation.
   * w2_gradients     -- parity unpinned beyond finite differences of the
                         oracle's own value (the discretised pushforward adds an
                         envelope error of the order of the discretisation).

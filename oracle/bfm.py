@@ -161,6 +161,17 @@ def pushforward(density: np.ndarray, T: Sequence[np.ndarray]) -> np.ndarray:
     return rho.reshape(shape)
 
 
+def displacement_interpolant(density: np.ndarray, pc: np.ndarray, t: float) -> np.ndarray:
+    """rho_t = S_t # density with S_t(x) = t T(x) + (1 - t) x, T the discrete
+    map of pc (``transport_map``): the displacement interpolant between the
+    two marginals of the transport (Section 4.3, optimal transport of
+    images), deposited like the method's pushforward."""
+    xs = centres(density.shape)
+    T = transport_map(pc)
+    S = [t * Ta + (1.0 - t) * x for Ta, x in zip(T, xs)]
+    return pushforward(density, S)
+
+
 def primal_cost(density: np.ndarray, T: Sequence[np.ndarray]) -> float:
     """P = integral of 1/2 |x - T(x)|^2 d(density)."""
     xs = centres(density.shape)

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
-            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass"]
+            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass", "bfm_interpolate"]
 
 
 class BFMError(RuntimeError):
@@ -80,6 +80,7 @@ def lib():
         L.bfm_plan_tuning.argtypes = [vp, P(i32)]
         L.bfm_plan_set_tuning.argtypes = [vp, P(i32)]
         L.bfm_ctransform_pass.argtypes = [vp, i32, vp, vp, vp, P(ctypes.c_double), vp, sz, vp]
+        L.bfm_interpolate.argtypes = [vp, vp, vp, i32, P(ctypes.c_double), vp, vp, sz, vp]
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
                                         P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
@@ -214,6 +215,19 @@ class Plan:
                 flat[3 * a + k] = int(tri[k])
         _check(lib().bfm_plan_set_tuning(self._h, flat))
 
+    def interpolate(self, phi, mu, times):
+        """Displacement interpolants rho_t = S_t # mu, S_t = t T + (1 - t) id,
+        for each t in ``times`` (``bfm_interpolate``); T is the map of phi."""
+        phi = self._field(phi, "phi")
+        mu = self._field(mu, "mu")
+        ts = [float(t) for t in times]
+        out = torch.empty((len(ts),) + self.shape, dtype=self.dtype, device=mu.device)
+        arr = (ctypes.c_double * max(1, len(ts)))(*ts)
+        ws = self.workspace(mu.device)
+        _check(lib().bfm_interpolate(self._h, _ptr(phi), _ptr(mu), len(ts), arr, _ptr(out), _ptr(ws), self.ws_bytes,
+                                     _stream(mu.device)))
+        return out
+
     def ctransform_pass(self, f, pass_: int, out=None, weight=None, want_sum: bool = False):
         """One pass of the column-blocked 2D transform (``bfm_ctransform_pass``):
         pass 0 maps a row-major field to the column-blocked column pass of -f,
@@ -325,6 +339,11 @@ def solve(mu: torch.Tensor, nu: torch.Tensor, phi_init=None, return_map=True, **
 
 def ctransform(f: torch.Tensor) -> torch.Tensor:
     return plan_for(f.shape, f.dtype).ctransform(f)
+
+
+def interpolate(phi: torch.Tensor, mu: torch.Tensor, times) -> torch.Tensor:
+    """Displacement interpolants between mu and the target of the map of phi."""
+    return plan_for(mu.shape, mu.dtype).interpolate(phi, mu, times)
 
 
 def pushforward(phic: torch.Tensor, mass: torch.Tensor, return_map=True):

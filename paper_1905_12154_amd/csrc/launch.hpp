@@ -61,7 +61,7 @@ long long dct_fused_parts(int n0, long long N, size_t esz);
 // map, pushforward, reductions, controller (pushforward.hip, reduce.hip)
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream);
+                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream, T tmix = T(1));
 template <typename T>
 hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long long N, double *part1,
                        double *part2, int nblocks, const int32_t *done, hipStream_t stream);

@@ -11,7 +11,9 @@
 //     split over the 2^d cell centres around T(x) with the multilinear
 //     weights (exact mass conservation up to rounding).
 // Fused float64 partial sums: sum mu |x - T|^2 / 2 (primal cost of the map)
-// and sum mu phi^c (the second term of J).
+// and sum mu phi^c (the second term of J).  With tmix != 1 the map is the
+// displacement interpolant S_t(x) = t T(x) + (1 - t) x (Section 4.3,
+// optimal transport of images), t = tmix.
 //
 // Deposition: source cells are processed by compact tiles (32 x 32 in 2D,
 // 8 x 8 x 8 in 3D).  Where the map compresses mass, many sources of a tile
@@ -82,7 +84,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kRedBlock)
 splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
              T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
-             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done)
+             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done, T tmix)
 {
     if (done != nullptr && *done) return;
     constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
@@ -176,7 +178,8 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                     d = (pc[id + str] - pc[id - str]) * (T(0.5) * fn);
                 const T x = (T(i) + T(0.5)) / fn;
                 const T lo_t = T(0.5) / fn;
-                const T t = fmin(fmax(x - d, lo_t), T(1) - lo_t);
+                T t = fmin(fmax(x - d, lo_t), T(1) - lo_t);
+                if (tmix != T(1)) t = x + tmix * (t - x);   // displacement interpolation: t T(x) + (1 - t) x
                 if (Tout != nullptr) Tout[(long long)a * g.N + id] = t;
                 sq += (x - t) * (x - t);
                 const T qq = t * fn - T(0.5);
@@ -301,23 +304,23 @@ long long splat_blocks(const Grid &g) {
 
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream)
+                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream, T tmix)
 {
     const long long nb = splat_blocks(g), nt = splat_ntiles(g);
     if (g.ndim == 2)
         hipLaunchKernelGGL((splat_kernel<T, 2>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
-                           rho, Tout, part_primal, part_pcsrc, done);
+                           rho, Tout, part_primal, part_pcsrc, done, tmix);
     else if (g.ndim == 3)
         hipLaunchKernelGGL((splat_kernel<T, 3>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
-                           rho, Tout, part_primal, part_pcsrc, done);
+                           rho, Tout, part_primal, part_pcsrc, done, tmix);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 template hipError_t launch_splat<float>(const Grid &, const float *, const float *, float *, float *, double *,
-                                        double *, int, const int32_t *, hipStream_t);
+                                        double *, int, const int32_t *, hipStream_t, float);
 template hipError_t launch_splat<double>(const Grid &, const double *, const double *, double *, double *,
-                                         double *, double *, int, const int32_t *, hipStream_t);
+                                         double *, double *, int, const int32_t *, hipStream_t, double);
 
 }  // namespace bfm

@@ -981,6 +981,39 @@ extern "C" bfm_status bfm_ctransform_pass(bfm_plan plan, int32_t pass, const voi
     return ct_pass_impl<float>(plan, pass, (const float *)in, (float *)out, (const float *)weight, host_sum, w, s);
 }
 
+template <typename T>
+static bfm_status interp_impl(bfm_plan P, const T *phi, const T *mu, int nt, const double *times, T *rho,
+                              const Ws &w, hipStream_t s)
+{
+    const Grid &g = P->g;
+    T *pc = (T *)w.pc;
+    HIP_TRY(ctransform_field<T>(g, phi, pc, nullptr, s, P->ct_cfg, (T *)w.f));
+    for (int k = 0; k < nt; ++k) {
+        T *r = rho + (size_t)k * g.N;
+        HIP_TRY(launch_fill<T>(r, g.N, T(0), s));
+        HIP_TRY(launch_splat<T>(g, pc, mu, r, nullptr, nullptr, nullptr, P->red_blocks, nullptr, s, (T)times[k]));
+    }
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_interpolate(bfm_plan plan, const void *phi, const void *mu, int32_t ntimes,
+                                      const double *times, void *rho, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || phi == nullptr || mu == nullptr || times == nullptr || rho == nullptr)
+        return fail(BFM_EINVAL, "NULL argument");
+    if (ntimes < 1) return fail(BFM_EINVAL, "ntimes = %d: need at least one time", ntimes);
+    for (int k = 0; k < ntimes; ++k)
+        if (!(times[k] >= 0.0 && times[k] <= 1.0)) return fail(BFM_EINVAL, "times[%d] = %g is not in [0, 1]", k, times[k]);
+    if (rho == phi || rho == mu) return fail(BFM_EINVAL, "rho must not alias phi or mu");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return interp_impl<double>(plan, (const double *)phi, (const double *)mu, ntimes, times, (double *)rho, w, s);
+    return interp_impl<float>(plan, (const float *)phi, (const float *)mu, ntimes, times, (float *)rho, w, s);
+}
+
 extern "C" bfm_status bfm_trace(bfm_plan plan, const void *workspace, size_t ws_bytes, double *host,
                                 int32_t max_records, int32_t *count, void *stream)
 {

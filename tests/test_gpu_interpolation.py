@@ -1,0 +1,67 @@
+"""Displacement interpolation on the GPU (bfm_interpolate) against the
+oracle's interpolant (Section 4.3, optimal transport of images)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfm as ob
+from paper_1905_12154_amd import bfm, workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+TIMES = [0.0, 0.2, 0.5, 0.75, 1.0]
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (48, 96), (12, 16, 18)])
+def test_interpolant_f64_matches_oracle(shape):
+    rng = np.random.default_rng(11)
+    mu = wl.random_gaussian_mixture(shape, 3, rng)
+    nu = wl.random_gaussian_mixture(shape, 2, rng)
+    o = ob.solve(mu, nu, ob.Params(max_iters=20))
+    pc = ob.ctransform(o.phi)
+    got = host(bfm.interpolate(cuda(o.phi), cuda(mu), TIMES))
+    for k, t in enumerate(TIMES):
+        ref = ob.displacement_interpolant(mu, pc, t)
+        assert np.max(np.abs(got[k] - ref)) <= 1e-11 * np.max(ref), t
+    assert np.max(np.abs(got[0] - mu)) <= 1e-12 * np.max(mu)
+
+
+def test_interpolant_f32_solve_256():
+    """After a float32 solve: mass is conserved in every frame, t = 0 gives
+    mu, t = 1 the pushforward primitive, and the frames agree with the
+    oracle's interpolant of the same potential to the float32 map error."""
+    mu, nu = wl.config_c5_pair(1, 256)
+    tmu, tnu = cuda(mu, torch.float32), cuda(nu, torch.float32)
+    r = bfm.solve(tmu, tnu, max_iters=60)
+    frames = bfm.interpolate(r.phi, tmu, TIMES)
+    mass = float(tmu.double().sum())
+    for k in range(len(TIMES)):
+        assert abs(float(frames[k].double().sum()) - mass) <= 1e-5 * mass
+    assert float((frames[0] - tmu).abs().max()) <= 1e-5 * float(tmu.max())
+    pc = bfm.ctransform(r.phi)
+    rho1, _, _ = bfm.pushforward(pc, tmu)
+    assert float((frames[-1] - rho1).abs().max()) <= 1e-5 * float(rho1.abs().max())
+    pco = ob.ctransform(host(r.phi))
+    for k, t in enumerate(TIMES):
+        ref = ob.displacement_interpolant(mu.astype(np.float32).astype(np.float64), pco, t)
+        d = np.abs(host(frames[k]) - ref)
+        assert d.sum() <= 1e-2 * np.abs(ref).sum(), t
+
+
+def test_interpolate_argument_errors():
+    plan = bfm.Plan((32, 32), torch.float64)
+    x = cuda(np.ones((32, 32)))
+    for bad in ([-0.1], [1.5], [float("nan")], []):
+        with pytest.raises(bfm.BFMError) as e:
+            plan.interpolate(x, x, bad)
+        assert e.value.status == bfm.BFM_EINVAL
