@@ -20,6 +20,13 @@ Pins (see tests/test_oracle_*.py):
                         against the exact discrete LP (HiGHS) on tiny grids,
                         the unconditional c-transform half of the monotone
                         chain, Gaussian-to-Gaussian affine maps.
+  * solve_ga         -- iterates c-concave and psi = phi^c by the brute-force
+                        transform (f^ccc = f^c), the double transform never
+                        lowers J, weak duality against the LP and
+                        feasibility, the exact two-disc cost, the first step
+                        equal to the phi-step of Algorithm 1, and the
+                        iteration ratio of Tables 5 and 6 (the
+                        back-and-forth iteration needs several times fewer).
   * displacement_interpolant -- t = 0 gives the density itself, t = 1 the
                         method's pushforward, whole-cell translations move by
                         t times the shift, mass is conserved, and the

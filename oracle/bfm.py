@@ -339,6 +339,52 @@ def solve(mu: np.ndarray, nu: np.ndarray, prm: Optional[Params] = None,
                   gap=gap, G=head["G"], sigma=sigma, iters=it, converged=converged, trace=trace)
 
 
+def solve_ga(mu: np.ndarray, nu: np.ndarray, prm: Optional[Params] = None,
+             phi_init: Optional[np.ndarray] = None) -> Result:
+    """Plain H^1 gradient ascent on J, the scheme Section 4.3 compares the
+    back-and-forth method with (Tables 5 and 6):
+
+        phi_{n+1/2} = phi_n + sigma grad J(phi_n),   phi_{n+1} = (phi_{n+1/2})^cc.
+
+    Only phi-space is visited.  The inner c-transform q = (phi_{n+1/2})^c is
+    also phi_{n+1}^c, because f^ccc = f^c (Lemma on c-transform properties),
+    so the head of iteration n+1 evaluates J(phi_{n+1}) with phi_{n+1}^c = q:
+    two c-transforms and one Poisson solve per iteration, as the paper counts
+    them.  sigma follows the Section 4.2 rule after each gradient step (the
+    increase J(phi_{n+1/2}) - J(phi_n) against sigma G_n); the head, gap,
+    stopping test and outputs are those of solve()."""
+    prm = prm or Params()
+    mu = np.asarray(mu, dtype=np.float64)
+    nu = np.asarray(nu, dtype=np.float64)
+    phi = np.zeros_like(mu) if phi_init is None else np.array(phi_init, dtype=np.float64)
+    sigma = prm.sigma0 if prm.sigma0 > 0 else initial_sigma(mu, nu)
+    pc = ctransform(phi)
+    trace = []
+    converged = False
+    it = 0
+    while True:
+        head = half_step(phi, mu, nu, sigma, prm, pc=pc)
+        gap = max(abs(head["P"] - head["J0"]), head["G"])
+        trace.append(dict(iter=it, dual=head["J0"], primal=head["P"], G=head["G"],
+                          gap=gap, sigma=sigma))
+        if prm.tol > 0 and gap < prm.tol:
+            converged = True
+            break
+        if it >= prm.max_iters:
+            break
+        phi_half = phi + sigma * head["g"]
+        q = ctransform(phi_half)
+        J1 = dual_value(phi_half, q, nu, mu)
+        trace[-1]["J_half"] = J1
+        sigma = update_sigma(sigma, J1 - head["J0"], head["G"], prm)
+        phi = ctransform(q)
+        pc = q
+        it += 1
+    m = float(np.mean(phi))
+    return Result(phi=phi - m, psi=head["pc"] + m, T=head["T"], dual=head["J0"], primal=head["P"],
+                  gap=gap, G=head["G"], sigma=sigma, iters=it, converged=converged, trace=trace)
+
+
 def w2_gradients(res: Result, shape: Sequence[int]):
     """Envelope gradients of W2^2 = 2 C(mu, nu) w.r.t. the grid density values:
     d/dmu = 2 cell_volume (psi - mean psi), d/dnu = 2 cell_volume (phi - mean phi)
