@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-interp", action="store_true", help="skip the 1024^2 displacement-interpolation leg")
     ap.add_argument("--interp-frames", type=int, default=11)
+    ap.add_argument("--no-ga", action="store_true",
+                    help="skip the back-and-forth versus gradient-ascent leg (two 1024^2 examples, float64)")
+    ap.add_argument("--ga-cap", type=int, default=3000, help="iteration cap of the gradient-ascent runs")
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
@@ -240,6 +243,46 @@ def interp_leg(iters, tol, nframes):
             "max_frame_mass_error": max(abs(float(f.double().sum()) - mass) / mass for f in frames)}
 
 
+def ga_leg(cap_bfm, cap_ga, errors=(1e-4, 1e-5, 1e-6)):
+    """Back-and-forth iteration against the plain H^1 gradient ascent on the
+    two 1024^2 examples of Tables 5 and 6 (float64): iterations and seconds
+    until the dual is within `err` of the exact transport cost.  A first solve
+    per method records the trace (every head's dual); each error level is
+    then timed as a solve of exactly that many iterations."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    out = {"workload": "two discs (cost 1/4) and one square to four squares (cost 1/16), 1024^2, float64",
+           "measure": "first iteration n with |J(phi_n) - exact cost| < err; seconds = solve of n iterations"}
+    for case, exact in (("two_discs", 0.25), ("square_to_four", 1.0 / 16.0)):
+        mu_h, nu_h = getattr(wl, case)(1024)
+        mu = torch.tensor(mu_h, dtype=torch.float64, device=dev)
+        nu = torch.tensor(nu_h, dtype=torch.float64, device=dev)
+        res = {}
+        for method, cap in (("bfm", cap_bfm), ("ga", cap_ga)):
+            plan = bfm.Plan(mu.shape, torch.float64, max_iters=cap, check_every=cap, method=method)
+            plan.autotune(dev)
+            plan.solve(mu, nu, return_map=False)
+            tr = plan.trace(dev)
+            row = {"cap": cap}
+            for err in errors:
+                n = next((int(e["iter"]) for e in tr if abs(e["dual"] - exact) < err), None)
+                if n is None:
+                    row["%g" % err] = {"iters": None, "seconds": None}
+                    continue
+                p = bfm.Plan(mu.shape, torch.float64, max_iters=n, check_every=max(n, 1), method=method)
+                p.autotune(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = p.solve(mu, nu, return_map=False)
+                torch.cuda.synchronize()
+                row["%g" % err] = {"iters": n, "seconds": time.perf_counter() - t0,
+                                   "error": abs(r.dual - exact)}
+            res[method] = row
+        out[case] = res
+    return out
+
+
 def cpu_baseline(n):
     """The float64 oracle, timed on a bounded sample of one iteration at the
     same grid: 64 lines of each c-transform pass (scaled to all lines), one
@@ -393,6 +436,8 @@ def main():
         out["c4_3d"] = c4_leg(args.c4_iters, not args.no_autotune)
     if not args.no_interp:
         out["interp_c2"] = interp_leg(2000, 1e-5, max(2, args.interp_frames))
+    if not args.no_ga:
+        out["bfm_vs_ga"] = ga_leg(40, args.ga_cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

@@ -51,6 +51,20 @@ typedef enum {
 
 typedef enum { BFM_F32 = 0, BFM_F64 = 1 } bfm_dtype;
 
+/* Iteration scheme of bfm_solve / bfm_solve_batched.
+ *   BFM_METHOD_BFM: the back-and-forth iteration of Algorithm 1: a gradient
+ *     step on J in phi-space, a c-transform, a gradient step on I in
+ *     psi-space, a c-transform (4 c-transforms, 2 Poisson solves per
+ *     iteration).
+ *   BFM_METHOD_GA: the plain H^1 gradient ascent on J that Section 4.3
+ *     compares against (Tables 5 and 6): phi_{n+1/2} = phi_n + sigma grad J(phi_n),
+ *     phi_{n+1} = (phi_{n+1/2})^cc.  The first c-transform of the double
+ *     transform is phi_{n+1}^c itself (a c-transform is idempotent after two
+ *     applications: f^ccc = f^c), so it serves the next head and an
+ *     iteration costs 2 c-transforms and 1 Poisson solve.  Same step rule,
+ *     gap and stopping test as the back-and-forth iteration. */
+typedef enum { BFM_METHOD_BFM = 0, BFM_METHOD_GA = 1 } bfm_method;
+
 /* Solver parameters.  Defaults (bfm_params_init) are the paper's Section 4.2
  * constants: sigma_min = 0.01, beta1 = 1/4, beta2 = 3/4, alpha1 = 5/4,
  * alpha2 = 4/5, and sigma0 <= 0 meaning 8 min(1/max mu, 1/max nu). */
@@ -58,13 +72,13 @@ typedef struct {
     int32_t ndim;          /* 2 or 3 */
     int32_t shape[3];      /* cells per axis, each 4 <= n <= 4096 and of the form 2^a 3^b */
     int32_t dtype;         /* bfm_dtype: storage and arithmetic type of fields; sums are float64 */
-    int32_t max_iters;     /* full back-and-forth iterations (phi-step + psi-step) */
+    int32_t max_iters;     /* full iterations (BFM: phi-step + psi-step; GA: one gradient step + cc) */
     double tol;            /* stop when gap < tol; 0 runs max_iters iterations */
     double sigma0;         /* initial step; <= 0 selects 8 min(1/max mu, 1/max nu) */
     double sigma_min;
     double beta1, beta2, alpha1, alpha2;
     int32_t check_every;   /* iterations enqueued between host reads of the stop flag (>= 1) */
-    int32_t reserved;
+    int32_t method;        /* bfm_method; default BFM_METHOD_BFM */
 } bfm_params;
 
 /* Per-solve report (host struct). gap = max(|primal - dual|, G) at the last
@@ -96,7 +110,8 @@ void bfm_plan_destroy(bfm_plan plan);
 /* Bytes of device workspace every call on this plan needs. */
 bfm_status bfm_plan_workspace_bytes(bfm_plan plan, size_t *bytes);
 
-/* Back-and-forth solve (Algorithm 1, step rule of Section 4.2).
+/* Back-and-forth solve (Algorithm 1, step rule of Section 4.2), or with
+ * params.method = BFM_METHOD_GA the plain gradient ascent of Section 4.3.
  *   mu, nu     device, N elements each: source and target densities (read only).
  *              Rejected with BFM_EINVAL (before any iteration) if a value is
  *              negative or non-finite or |cell_volume*sum - 1| > 1e-5.
@@ -118,7 +133,7 @@ bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *
  * parallel branches) and the graph is replayed; each problem keeps its own
  * step size, gap and stop flag, and a problem that has stopped turns into
  * no-ops.  Stop flags are read on the host between replays.
- *   plans       npairs plans (any shapes; same dtype and max_iters; tol may differ).
+ *   plans       npairs plans (any shapes; same dtype and max_iters; tol and method may differ).
  *   mu .. T     host arrays of npairs device pointers (T may be NULL, or
  *               hold NULL entries); same meaning as in bfm_solve.
  *   workspaces  host array of npairs distinct device workspaces;

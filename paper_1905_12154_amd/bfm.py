@@ -38,7 +38,10 @@ class Params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("sigma0", ctypes.c_double),
                 ("sigma_min", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("alpha1", ctypes.c_double), ("alpha2", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("method", ctypes.c_int32)]
+
+
+METHODS = {"bfm": 0, "ga": 1}
 
 
 class Result(ctypes.Structure):
@@ -126,8 +129,10 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], dtype=torch.float32, max_iters: int = 60, tol: float = 0.0,
                  sigma0: float = 0.0, sigma_min: float = 0.01, beta1: float = 0.25, beta2: float = 0.75,
-                 alpha1: float = 1.25, alpha2: float = 0.8, check_every: int = 8):
+                 alpha1: float = 1.25, alpha2: float = 0.8, check_every: int = 8, method: str = "bfm"):
         L = lib()
+        if method not in METHODS:
+            raise ValueError("method must be one of %s" % sorted(METHODS))
         self.shape = tuple(int(s) for s in shape)
         self.code = _dtype_code(dtype)
         self.dtype = _torch_dtype(self.code)
@@ -137,6 +142,8 @@ class Plan:
         p.max_iters, p.tol, p.sigma0, p.sigma_min = int(max_iters), float(tol), float(sigma0), float(sigma_min)
         p.beta1, p.beta2, p.alpha1, p.alpha2 = float(beta1), float(beta2), float(alpha1), float(alpha2)
         p.check_every = int(check_every)
+        p.method = METHODS[method]
+        self.method = method
         self.params = p
         h = ctypes.c_void_p()
         _check(L.bfm_plan_create(ctypes.byref(p), ctypes.byref(h)))
@@ -333,7 +340,8 @@ def plan_for(shape, dtype, **kw) -> Plan:
 
 
 def solve(mu: torch.Tensor, nu: torch.Tensor, phi_init=None, return_map=True, **kw) -> SolveResult:
-    """Back-and-forth solve of quadratic-cost OT between grid densities."""
+    """Quadratic-cost OT between grid densities: the back-and-forth iteration,
+    or with ``method="ga"`` the plain H^1 gradient ascent it is compared with."""
     return plan_for(mu.shape, mu.dtype, **kw).solve(mu, nu, phi_init=phi_init, return_map=return_map)
 
 
@@ -356,7 +364,7 @@ def poisson_neumann(f: torch.Tensor):
 
 def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_iters: int = 100,
                   tol: float = 0.0, iters_per_graph: int = 8, return_map: bool = False,
-                  workspaces: Optional[List[torch.Tensor]] = None) -> List[SolveResult]:
+                  workspaces: Optional[List[torch.Tensor]] = None, method: str = "bfm") -> List[SolveResult]:
     """Solve many independent problems together (``bfm_solve_batched``): one
     HIP graph replay advances every problem by ``iters_per_graph`` iterations.
     Problems may have different shapes; all share dtype and ``max_iters``."""
@@ -364,7 +372,7 @@ def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_
     if n != len(nus) or n == 0:
         raise ValueError("need the same positive number of mu and nu tensors")
     dev = mus[0].device
-    plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol) for m in mus]
+    plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol, method=method) for m in mus]
     mus = [p._field(m, "mu[%d]" % i) for i, (p, m) in enumerate(zip(plans, mus))]
     nus = [p._field(v, "nu[%d]" % i) for i, (p, v) in enumerate(zip(plans, nus))]
     phis = [torch.empty_like(m) for m in mus]

@@ -83,10 +83,13 @@ enum CtrlMode {
     CTRL_STEP_PHI,     // J(phi_{n+1/2}) and the sigma update
     CTRL_HEAD_PSI,     // I(psi_{n+1/2}), G
     CTRL_STEP_PSI,     // I(psi_{n+1}), sigma update, iteration count
-    CTRL_MEANS         // mean_a, mean_b from S_MEAN_A / S_MEAN_B
+    CTRL_MEANS,        // mean_a, mean_b from S_MEAN_A / S_MEAN_B
+    CTRL_GA_NEXT       // gradient ascent: sum phi_{n+1} * nu from S_Q_TGT (prm.nqt partials)
+                       // kept for the next head, iteration count
 };
 // Head modes OR'ed with this flag take sum p * tgt from the previous step's
-// sum q * src (the same products: p of a head is q of the step before it).
+// sum q * src (the same products: p of a head is q of the step before it),
+// or, in gradient ascent, from the sum CTRL_GA_NEXT kept.
 constexpr int CTRL_REUSE_DOT = 0x100;
 
 struct CtrlParams {

@@ -270,6 +270,19 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
         }
         return;
     }
+    if (mode == CTRL_GA_NEXT) {
+        const double a = slot_reduce_sum(partials, sl, S_Q_TGT, prm.nqt, sh);
+        if (threadIdx.x == 0) {
+            if (!isfinite(a)) {
+                st->nonfinite = 1;
+                st->done = 1;
+                return;
+            }
+            st->q_src = a;
+            st->iter += 1;
+        }
+        return;
+    }
     if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
         const double a = slot_reduce_sum(partials, sl, S_Q_TGT, prm.nqt, sh);
         const double b = slot_reduce_sum(partials, sl, S_Q_SRC, prm.nqs, sh);

@@ -107,6 +107,8 @@ static bfm_status check_params(const bfm_params *p)
     if (!(p->alpha1 > 1.0 && p->alpha2 > 0.0 && p->alpha2 < 1.0) || !isfinite(p->alpha1))
         return fail(BFM_EINVAL, "need alpha1 > 1 and 0 < alpha2 < 1");
     if (p->check_every < 1) return fail(BFM_EINVAL, "check_every must be >= 1");
+    if (p->method != BFM_METHOD_BFM && p->method != BFM_METHOD_GA)
+        return fail(BFM_EINVAL, "method must be BFM_METHOD_BFM or BFM_METHOD_GA (got %d)", p->method);
     return BFM_OK;
 }
 
@@ -126,6 +128,7 @@ extern "C" bfm_status bfm_params_init(bfm_params *p, int32_t ndim, const int32_t
     p->alpha1 = 1.25;
     p->alpha2 = 0.8;
     p->check_every = 8;
+    p->method = BFM_METHOD_BFM;
     return check_params(p);
 }
 
@@ -361,9 +364,11 @@ static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *upda
 //   head:  pc = p^c, J(p), map + pushforward rho = T#src, primal cost,
 //          H^1 gradient g of tgt - rho and G; controller `head_mode`;
 //   step:  p <- p + sigma g, q = p^c, J(p), controller `step_mode`.
+// head_ct = false takes pc as already holding p^c (gradient ascent, where
+// the previous step left it there).
 template <typename T>
 static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T *tgt, T *q, int head_mode,
-                            int step_mode, bool head_only, bool head_dot, hipStream_t s)
+                            int step_mode, bool head_only, bool head_dot, hipStream_t s, bool head_ct = true)
 {
     const Grid &g = P->g;
     const int32_t *done = &w.st->done;
@@ -371,7 +376,8 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     T *pc = (T *)w.pc, *rho = (T *)w.rho, *F = (T *)w.f;
     const CtrlParams cp = ctrl_params(P);
     hipError_t e;
-    if ((e = ctransform_field<T>(g, p, pc, done, s, P->ct_cfg, F)) != hipSuccess) return e;   // F is free here
+    if (head_ct && (e = ctransform_field<T>(g, p, pc, done, s, P->ct_cfg, F)) != hipSuccess)
+        return e;   // F is free here
     if (head_dot &&
         (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
@@ -436,11 +442,48 @@ static bfm_status solve_begin(bfm_plan P, const T *mu, const T *nu, const T *phi
     return check_inputs(hs);
 }
 
+// One iteration of the plain H^1 gradient ascent of Section 4.3 (the scheme
+// Tables 5 and 6 compare with): the phi half-step of Algorithm 1 with its
+// c-transform written to pc (q = phi_{n+1/2}^c, the stepped J and the sigma
+// update), then phi_{n+1} = q^c = phi_{n+1/2}^cc.  Since f^ccc = f^c, q is
+// phi_{n+1}^c and serves the next head, which therefore computes no
+// c-transform: 2 c-transforms and 1 Poisson solve per iteration.  The sum
+// <phi_{n+1}, nu> of the next head is fused into the pass writing phi_{n+1}.
+template <typename T>
+static hipError_t ga_iteration(bfm_plan P, const Ws &w, const T *mu, const T *nu, T *phi, bool first, hipStream_t s)
+{
+    const Grid &g = P->g;
+    const int32_t *done = &w.st->done;
+    T *pc = (T *)w.pc, *F = (T *)w.f;
+    hipError_t e;
+    if ((e = half_step<T>(P, w, phi, mu, nu, pc, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, first, s, first)) !=
+        hipSuccess)
+        return e;
+    int nd = 0;
+    const bool al = (((uintptr_t)nu) & 15) == 0;
+    if ((e = ctransform_field<T>(g, pc, phi, done, s, P->ct_cfg, F, al ? nu : nullptr, w.slot(S_Q_TGT), &nd)) !=
+        hipSuccess)
+        return e;   // F is free after the step
+    if (nd > w.slot_len) return hipErrorInvalidValue;
+    if (nd == 0 &&
+        (e = launch_dot2<T>(phi, nu, nullptr, nullptr, g.N, w.slot(S_Q_TGT), nullptr, P->red_blocks, done, s)) !=
+            hipSuccess)
+        return e;
+    CtrlParams cs = ctrl_params(P);
+    cs.nqt = nd > 0 ? nd : P->red_blocks;
+    return launch_ctrl(w.st, w.part, w.gpart, CTRL_GA_NEXT, cs, w.trace, s);
+}
+
 template <typename T>
 static hipError_t enqueue_iterations(bfm_plan P, const Ws &w, const T *mu, const T *nu, T *phi, T *psi, int it0,
                                      int count, hipStream_t s)
 {
     hipError_t e;
+    if (P->prm.method == BFM_METHOD_GA) {
+        for (int it = it0; it < it0 + count; ++it)
+            if ((e = ga_iteration<T>(P, w, mu, nu, phi, it == 0, s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     for (int it = it0; it < it0 + count; ++it) {
         if ((e = half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, it == 0, s)) != hipSuccess)
             return e;
@@ -454,7 +497,9 @@ template <typename T>
 static hipError_t enqueue_final_head(bfm_plan P, const Ws &w, const T *mu, const T *nu, T *phi, T *psi, int it,
                                      hipStream_t s)
 {
-    return half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, true, it == 0, s);
+    // gradient ascent keeps phi^c in pc from the last step
+    return half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, true, it == 0, s,
+                        P->prm.method != BFM_METHOD_GA || it == 0);
 }
 
 template <typename T>

@@ -42,6 +42,7 @@ def test_params_defaults_are_paper_constants(shape):
     assert st == bfm.BFM_OK
     assert (p.sigma_min, p.beta1, p.beta2, p.alpha1, p.alpha2) == (0.01, 0.25, 0.75, 1.25, 0.8)
     assert p.sigma0 == 0.0 and p.tol == 0.0
+    assert p.method == bfm.METHODS["bfm"] == 0
 
 
 @pytest.mark.parametrize("shape", [(5, 8), (64, 8192), (2, 64), (64,), (7, 7, 7), (64, 64, 64, 64)])
@@ -61,7 +62,8 @@ def test_bad_shapes_rejected(shape):
 
 @pytest.mark.parametrize("field,value", [("dtype", 7), ("beta1", 0.9), ("alpha1", 0.5), ("alpha2", 1.5),
                                          ("sigma_min", 0.0), ("tol", -1.0), ("check_every", 0),
-                                         ("max_iters", -3), ("sigma0", float("nan"))])
+                                         ("max_iters", -3), ("sigma0", float("nan")), ("method", 2),
+                                         ("method", -1)])
 def test_bad_parameters_rejected(field, value):
     st, p = _params((32, 32))
     setattr(p, field, value)
@@ -107,3 +109,6 @@ def test_plan_python_validation():
         plan.ctransform(__import__("torch").zeros(32, 32))
     with pytest.raises(bfm.BFMError):
         bfm.Plan((31, 32))
+    with pytest.raises(ValueError):
+        bfm.Plan((32, 32), method="newton")
+    assert bfm.Plan((32, 32), method="ga").params.method == 1

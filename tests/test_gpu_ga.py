@@ -1,0 +1,138 @@
+"""The plain H^1 gradient ascent (the comparison scheme of Section 4.3,
+Tables 5 and 6) on the HIP path against the float64 oracle's solve_ga.
+
+float64: per-iteration dual, J(phi_{n+1/2}) and sigma to 1e-10 (the step
+rule compares the increase with sigma G, so equal sigma sequences show the
+two loops take the same decisions), potentials to 1e-6 after 40 iterations,
+the map to 1e-3 cells.  float32 fields: W2^2 to 1e-4 relative."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfm as ob
+from paper_1905_12154_amd import bfm, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _both(mu, nu, dtype, iters, **kw):
+    plan = bfm.plan_for(mu.shape, dtype, max_iters=iters, method="ga", **kw)
+    r = plan.solve(cuda(mu, dtype), cuda(nu, dtype))
+    tr = plan.trace(torch.device(DEV))
+    o = ob.solve_ga(mu, nu, ob.Params(max_iters=iters, **kw))
+    return r, tr, o
+
+
+def test_ga_parity_c1_f64():
+    mu, nu = wl.config_c1()
+    r, tr, o = _both(mu, nu, torch.float64, 40)
+    assert r.iters == o.iters == 40
+    assert len(tr) == len(o.trace) == 41
+    for g, e in zip(tr, o.trace):
+        assert int(g["iter"]) == e["iter"]
+        assert abs(g["dual"] - e["dual"]) <= 1e-10
+        assert abs(g["G"] - e["G"]) <= 1e-10 * max(1.0, e["G"])
+        assert g["sigma"] == pytest.approx(e["sigma"], rel=1e-12)
+        if "J_half" in e:
+            assert abs(g["J_half"] - e["J_half"]) <= 1e-10
+        assert np.isnan(g["I_new"])   # no psi-step in this scheme
+    assert abs(r.w2sq - o.w2sq) <= 1e-5 * abs(o.w2sq)
+    assert np.max(np.abs(host(r.phi) - o.phi)) <= 1e-6
+    assert np.max(np.abs(host(r.psi) - o.psi)) <= 1e-6
+    for a in range(2):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * 64 <= 1e-3
+
+
+def test_ga_iterates_are_c_concave_on_device():
+    # phi_{n+1} = (phi_{n+1/2})^cc: the device c-transform of the returned phi
+    # is the returned psi (which the loop never computed from phi itself)
+    mu, nu = wl.config_c1()
+    r = bfm.solve(cuda(mu), cuda(nu), max_iters=9, method="ga")
+    phic = bfm.ctransform(r.phi)
+    assert torch.max(torch.abs(phic - r.psi)).item() <= 1e-13
+
+
+@pytest.mark.parametrize("case,n,exact", [("two_discs", 128, 0.25), ("square_to_four", 128, 1 / 16)])
+def test_ga_same_iterations_to_cost_error_as_oracle(case, n, exact):
+    # the measure of Tables 5 and 6: first iteration with |D_n - exact| < err
+    mu, nu = getattr(wl, case)(n)
+    r, tr, o = _both(mu, nu, torch.float64, 200)
+
+    def first(trace, tol):
+        return next((int(e["iter"]) for e in trace if abs(e["dual"] - exact) < tol), None)
+
+    for err in (1e-3, 1e-4):
+        assert first(tr, err) == first(o.trace, err) is not None
+
+
+def test_ga_stop_rule_same_iteration_as_oracle():
+    mu, nu = wl.two_discs(64)
+    r, tr, o = _both(mu, nu, torch.float64, 200, tol=1e-4)
+    assert r.converged and o.converged
+    assert r.iters == o.iters < 200
+    assert abs(r.gap - o.gap) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(96, 384), (6, 4)])
+def test_ga_parity_rectangular(shape):
+    rng = np.random.default_rng(12)
+    mu = wl.random_gaussian_mixture(shape, 3, rng)
+    nu = wl.random_gaussian_mixture(shape, 2, rng)
+    r, tr, o = _both(mu, nu, torch.float64, 15)
+    assert abs(r.dual - o.dual) <= 1e-10
+    assert all(abs(g["dual"] - e["dual"]) <= 1e-10 for g, e in zip(tr, o.trace))
+    for a in range(2):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * shape[a] <= 1e-3
+
+
+def test_ga_parity_3d_f64():
+    rng = np.random.default_rng(4)
+    shape = (16, 24, 18)
+    mu = wl.random_gaussian_mixture(shape, 2, rng)
+    nu = wl.random_gaussian_mixture(shape, 3, rng)
+    r, tr, o = _both(mu, nu, torch.float64, 10)
+    assert all(abs(g["dual"] - e["dual"]) <= 1e-10 for g, e in zip(tr, o.trace))
+    for a in range(3):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * shape[a] <= 1e-3
+
+
+def test_ga_f32_error_vs_oracle():
+    mu, nu = wl.config_c1()
+    r = bfm.solve(cuda(mu, torch.float32), cuda(nu, torch.float32), max_iters=40, method="ga")
+    o = ob.solve_ga(mu, nu, ob.Params(max_iters=40))
+    assert abs(r.w2sq - o.w2sq) <= 1e-4 * o.w2sq
+    for a in range(2):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * 64 <= 0.05
+
+
+def test_ga_zero_iterations_and_warm_start():
+    mu, nu = wl.config_c1()
+    r0 = bfm.solve(cuda(mu), cuda(nu), max_iters=0, method="ga")
+    o0 = ob.solve_ga(mu, nu, ob.Params(max_iters=0))
+    assert r0.iters == 0 and r0.dual == 0.0 == o0.dual
+    r1 = bfm.solve(cuda(mu), cuda(nu), max_iters=10, method="ga")
+    r2 = bfm.solve(cuda(mu), cuda(nu), max_iters=0, phi_init=r1.phi, method="ga")
+    assert abs(r2.dual - r1.dual) <= 1e-13
+
+
+def test_ga_batched_matches_single():
+    rng = np.random.default_rng(3)
+    pairs = [wl.config_c1(), (wl.random_gaussian_mixture((48, 64), 2, rng),
+                              wl.random_gaussian_mixture((48, 64), 3, rng))]
+    rs = bfm.solve_batched([cuda(m) for m, _ in pairs], [cuda(v) for _, v in pairs], max_iters=20,
+                           iters_per_graph=4, method="ga")
+    for (mu, nu), rb in zip(pairs, rs):
+        o = ob.solve_ga(mu, nu, ob.Params(max_iters=20))
+        assert rb.iters == 20
+        assert abs(rb.dual - o.dual) <= 1e-10
+        assert np.max(np.abs(host(rb.phi) - o.phi)) <= 1e-6
