@@ -27,6 +27,14 @@ Pins (see tests/test_oracle_*.py):
                         equal to the phi-step of Algorithm 1, and the
                         iteration ratio of Tables 5 and 6 (the
                         back-and-forth iteration needs several times fewer).
+  * power costs      -- (eq. p_costs, powers=...) the separable transform
+                        against the non-separable definition, p = 2 equal to
+                        the quadratic line minimum, c-transform identities, the
+                        map of a linear potential (a translation inverting
+                        h'), the primal cost of a translation, exact costs of
+                        translations (Jensen), weak duality against the LP,
+                        and the crossing discs moving along one axis only at
+                        cost 1/24 for exponents (3, 1.1).
   * displacement_interpolant -- t = 0 gives the density itself, t = 1 the
                         method's pushforward, whole-cell translations move by
                         t times the shift, mass is conserved, and the

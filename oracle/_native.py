@@ -32,6 +32,9 @@ def lib():
         L.oracle_line_min.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_double]
         L.oracle_line_min.restype = None
+        L.oracle_line_min_p.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_double, ctypes.c_double]
+        L.oracle_line_min_p.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L

@@ -35,7 +35,7 @@ import ctypes
 import math
 import os
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 import scipy.fft
@@ -85,25 +85,53 @@ def line_min(u: np.ndarray, axis: int) -> np.ndarray:
     return np.moveaxis(out, -1, axis)
 
 
-def ctransform(f: np.ndarray) -> np.ndarray:
-    """f^c(x) = min_y 1/2|x - y|^2 - f(y) over all grid points y.
+def line_min_p(u: np.ndarray, axis: int, p: float) -> np.ndarray:
+    """min over y on the line through x along ``axis`` of |x_a - y_a|^p / p + u(y)
+    (the one-dimensional step for the power cost of eq. p_costs)."""
+    n = u.shape[axis]
+    v = np.ascontiguousarray(np.moveaxis(np.asarray(u, dtype=np.float64), axis, -1))
+    out = np.empty_like(v)
+    _native.lib().oracle_line_min_p(v.ctypes.data, out.ctypes.data, v.size // n, n, 1.0 / n, float(p))
+    return np.moveaxis(out, -1, axis)
+
+
+def _powers(ndim: int, powers) -> List[float]:
+    """Per-axis exponents of the separable cost sum_a |x_a - y_a|^{p_a} / p_a
+    (eq. p_costs); None is the quadratic cost, p_a = 2 on every axis."""
+    if powers is None:
+        return [2.0] * ndim
+    pw = [float(q) for q in powers][:ndim]
+    assert len(pw) == ndim and all(q > 1.0 for q in pw)
+    return pw
+
+
+def ctransform(f: np.ndarray, powers=None) -> np.ndarray:
+    """f^c(x) = min_y c(x, y) - f(y) over all grid points y, with
+    c(x, y) = 1/2|x - y|^2, or sum_a |x_a - y_a|^{p_a} / p_a (eq. p_costs).
 
     Separable decomposition (Section 4.1): start from u = -f and take the
     one-dimensional minimum along the last axis, then along each earlier axis;
     the iterated minimum equals the minimum over the whole grid."""
     u = -np.asarray(f, dtype=np.float64)
+    pw = _powers(u.ndim, powers)
     for axis in reversed(range(u.ndim)):
-        u = line_min(u, axis)
+        u = line_min(u, axis) if pw[axis] == 2.0 else line_min_p(u, axis, pw[axis])
     return u
 
 
-def ctransform_bruteforce(f: np.ndarray) -> np.ndarray:
-    """Non-separable O(N^2) version of the same definition (tiny grids only)."""
-    shape = f.shape
+def cost_matrix(shape: Sequence[int], powers=None) -> np.ndarray:
+    """c(x_i, y_j) over all pairs of grid points (tiny grids only)."""
+    pw = _powers(len(shape), powers)
     xs = np.stack([x.ravel() for x in np.meshgrid(*[(np.arange(n) + 0.5) / n for n in shape],
                                                     indexing="ij")], axis=1)
-    c = 0.5 * ((xs[:, None, :] - xs[None, :, :]) ** 2).sum(-1)
-    return (c - f.ravel()[None, :]).min(axis=1).reshape(shape)
+    d = np.abs(xs[:, None, :] - xs[None, :, :])
+    return sum(d[..., a] ** pw[a] / pw[a] for a in range(len(shape)))
+
+
+def ctransform_bruteforce(f: np.ndarray, powers=None) -> np.ndarray:
+    """Non-separable O(N^2) version of the same definition (tiny grids only)."""
+    c = cost_matrix(f.shape, powers)
+    return (c - f.ravel()[None, :]).min(axis=1).reshape(f.shape)
 
 
 # ---------------------------------------------------------------------------
@@ -124,13 +152,18 @@ def grad_fd(p: np.ndarray) -> List[np.ndarray]:
     return out
 
 
-def transport_map(pc: np.ndarray) -> List[np.ndarray]:
-    """T(x) = x - grad p^c(x), clamped to [h/2, 1 - h/2] per axis."""
+def transport_map(pc: np.ndarray, powers=None) -> List[np.ndarray]:
+    """T(x) = x - (grad h)^{-1}(grad p^c(x)) (Lemma on c-transform properties
+    (ii)), clamped to [h/2, 1 - h/2] per axis.  For the quadratic cost
+    (grad h)^{-1} is the identity; for h_a(z) = |z|^p / p, h_a'(z) =
+    sign(z)|z|^{p-1}, whose inverse is g -> sign(g)|g|^{1/(p-1)}."""
     xs = centres(pc.shape)
+    pw = _powers(pc.ndim, powers)
     out = []
     for a, (x, g) in enumerate(zip(xs, grad_fd(pc))):
         h = 1.0 / pc.shape[a]
-        out.append(np.clip(x - g, 0.5 * h, 1.0 - 0.5 * h))
+        disp = g if pw[a] == 2.0 else np.sign(g) * np.abs(g) ** (1.0 / (pw[a] - 1.0))
+        out.append(np.clip(x - disp, 0.5 * h, 1.0 - 0.5 * h))
     return out
 
 
@@ -161,22 +194,27 @@ def pushforward(density: np.ndarray, T: Sequence[np.ndarray]) -> np.ndarray:
     return rho.reshape(shape)
 
 
-def displacement_interpolant(density: np.ndarray, pc: np.ndarray, t: float) -> np.ndarray:
+def displacement_interpolant(density: np.ndarray, pc: np.ndarray, t: float, powers=None) -> np.ndarray:
     """rho_t = S_t # density with S_t(x) = t T(x) + (1 - t) x, T the discrete
     map of pc (``transport_map``): the displacement interpolant between the
     two marginals of the transport (Section 4.3, optimal transport of
     images), deposited like the method's pushforward."""
     xs = centres(density.shape)
-    T = transport_map(pc)
+    T = transport_map(pc, powers)
     S = [t * Ta + (1.0 - t) * x for Ta, x in zip(T, xs)]
     return pushforward(density, S)
 
 
-def primal_cost(density: np.ndarray, T: Sequence[np.ndarray]) -> float:
-    """P = integral of 1/2 |x - T(x)|^2 d(density)."""
+def primal_cost(density: np.ndarray, T: Sequence[np.ndarray], powers=None) -> float:
+    """P = integral of c(x, T(x)) d(density): 1/2 |x - T(x)|^2, or
+    sum_a |x_a - T_a(x)|^{p_a} / p_a."""
     xs = centres(density.shape)
-    sq = sum((x - t) ** 2 for x, t in zip(xs, T))
-    return cell_vol(density.shape) * float(np.sum(density * 0.5 * sq))
+    if powers is None:
+        sq = sum((x - t) ** 2 for x, t in zip(xs, T))
+        return cell_vol(density.shape) * float(np.sum(density * 0.5 * sq))
+    pw = _powers(density.ndim, powers)
+    c = sum(np.abs(x - t) ** q / q for x, t, q in zip(xs, T, pw))
+    return cell_vol(density.shape) * float(np.sum(density * c))
 
 
 # ---------------------------------------------------------------------------
@@ -230,6 +268,7 @@ class Params:
     beta2: float = 0.75
     alpha1: float = 1.25
     alpha2: float = 0.8
+    powers: Optional[Tuple[float, ...]] = None   # eq. p_costs exponents per axis; None: quadratic
 
 
 def initial_sigma(mu: np.ndarray, nu: np.ndarray) -> float:
@@ -278,11 +317,11 @@ def half_step(p, src, tgt, sigma, prm: Params, pc=None):
     Returns a dict with the head quantities (at p) and the stepped potential
     p + sigma grad J(p) together with its c-transform."""
     if pc is None:
-        pc = ctransform(p)
+        pc = ctransform(p, prm.powers)
     J0 = dual_value(p, pc, tgt, src)
-    T = transport_map(pc)
+    T = transport_map(pc, prm.powers)
     rho = pushforward(src, T)
-    P = primal_cost(src, T)
+    P = primal_cost(src, T, prm.powers)
     g, G = poisson_neumann(tgt - rho)
     return dict(pc=pc, J0=J0, T=T, rho=rho, P=P, g=g, G=G)
 
@@ -321,14 +360,14 @@ def solve(mu: np.ndarray, nu: np.ndarray, prm: Optional[Params] = None,
             break
         # phi-step (Algorithm 1, first two lines)
         phi_half = phi + sigma * head["g"]
-        psi = ctransform(phi_half)
+        psi = ctransform(phi_half, prm.powers)
         J1 = dual_value(phi_half, psi, nu, mu)
         trace[-1]["J_half"] = J1
         sigma = update_sigma(sigma, J1 - head["J0"], head["G"], prm)
         # psi-step (Algorithm 1, last two lines)
         hp = half_step(psi, nu, mu, sigma, prm)
         psi_new = psi + sigma * hp["g"]
-        phi = ctransform(psi_new)
+        phi = ctransform(psi_new, prm.powers)
         I1 = dual_value(psi_new, phi, mu, nu)
         trace[-1].update(I_old=hp["J0"], I_new=I1, G_psi=hp["G"], sigma_psi=sigma)
         sigma = update_sigma(sigma, I1 - hp["J0"], hp["G"], prm)
@@ -358,7 +397,7 @@ def solve_ga(mu: np.ndarray, nu: np.ndarray, prm: Optional[Params] = None,
     nu = np.asarray(nu, dtype=np.float64)
     phi = np.zeros_like(mu) if phi_init is None else np.array(phi_init, dtype=np.float64)
     sigma = prm.sigma0 if prm.sigma0 > 0 else initial_sigma(mu, nu)
-    pc = ctransform(phi)
+    pc = ctransform(phi, prm.powers)
     trace = []
     converged = False
     it = 0
@@ -373,11 +412,11 @@ def solve_ga(mu: np.ndarray, nu: np.ndarray, prm: Optional[Params] = None,
         if it >= prm.max_iters:
             break
         phi_half = phi + sigma * head["g"]
-        q = ctransform(phi_half)
+        q = ctransform(phi_half, prm.powers)
         J1 = dual_value(phi_half, q, nu, mu)
         trace[-1]["J_half"] = J1
         sigma = update_sigma(sigma, J1 - head["J0"], head["G"], prm)
-        phi = ctransform(q)
+        phi = ctransform(q, prm.powers)
         pc = q
         it += 1
     m = float(np.mean(phi))

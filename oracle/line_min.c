@@ -34,6 +34,34 @@ void oracle_line_min(const double *in, double *out, int64_t nlines, int64_t n, d
     }
 }
 
+/*
+ * The same one-dimensional step for the separable power cost of eq. p_costs,
+ * h(z) = |z|^p / p with p > 1 (Section 4.1 for general separable costs;
+ * Section 4.3, optimal transport with general costs):
+ *
+ *     out[l][i] = min over all j of  |x_i - y_j|^p / p + in[l][j].
+ *
+ * Plain O(n^2) per line, from the definition, like oracle_line_min.
+ */
+void oracle_line_min_p(const double *in, double *out, int64_t nlines, int64_t n, double h, double p)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < nlines; ++l) {
+        const double *u = in + l * n;
+        double *o = out + l * n;
+        for (int64_t i = 0; i < n; ++i) {
+            const double xi = ((double)i + 0.5) * h;
+            double best = INFINITY;
+            for (int64_t j = 0; j < n; ++j) {
+                const double d = fabs(xi - ((double)j + 0.5) * h);
+                const double v = pow(d, p) / p + u[j];
+                best = v < best ? v : best;
+            }
+            o[i] = best;
+        }
+    }
+}
+
 int oracle_num_threads(void)
 {
     int t = 1;

@@ -149,6 +149,18 @@ def two_discs(n: int):
     return normalise(mu), normalise(nu)
 
 
+def crossing_discs(n: int):
+    """Section 4.3, optimal transport with general costs: mu is two uniform
+    discs of radius 1/8 centred at (1/4,1/4) and (3/4,3/4), nu two centred at
+    (1/4,3/4) and (3/4,1/4)."""
+    x0, x1 = cell_centres((n, n))
+    r2 = 1.0 / 64
+    disc = lambda c0, c1: (x0 - c0) ** 2 + (x1 - c1) ** 2 <= r2
+    mu = (disc(0.25, 0.25) | disc(0.75, 0.75)).astype(np.float64)
+    nu = (disc(0.25, 0.75) | disc(0.75, 0.25)).astype(np.float64)
+    return normalise(mu), normalise(nu)
+
+
 def two_balls(n: int):
     """Section 4.3: uniform balls of radius 1/8 centred at (1/4,..) and (3/4,..)."""
     x = cell_centres((n, n, n))
