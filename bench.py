@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-ga", action="store_true",
                     help="skip the back-and-forth versus gradient-ascent leg (two 1024^2 examples, float64)")
     ap.add_argument("--ga-cap", type=int, default=3000, help="iteration cap of the gradient-ascent runs")
+    ap.add_argument("--no-pcost", action="store_true", help="skip the power-cost leg (crossing discs, 1024^2)")
+    ap.add_argument("--pcost-iters", type=int, default=60)
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
@@ -283,6 +285,50 @@ def ga_leg(cap_bfm, cap_ga, errors=(1e-4, 1e-5, 1e-6)):
     return out
 
 
+def pcost_leg(iters, n=1024):
+    """Separable power costs (eq. p_costs) on the Section 4.3 example of two
+    pairs of discs at n^2, float32, for the paper's exponent pairs
+    (p_0, p_1) per array axis: `iters` iterations from phi = 0, the dual, the
+    gap, the motion along each axis, and the c-transform time (HIP events)
+    next to the quadratic one.  With (1.1, 3) the exact cost is (1/2)^3/3."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.crossing_discs(n)
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    x = (torch.arange(n, device=dev, dtype=torch.float32) + 0.5) / n
+    sup = mu > 0
+    rows = []
+    ct_ms = {}
+    for power in ((2.0, 2.0), (1.75, 2.25), (1.5, 2.5), (1.1, 3.0)):
+        plan = bfm.Plan(mu.shape, torch.float32, max_iters=iters, check_every=iters, power=power)
+        plan.solve(mu, nu, return_map=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = plan.solve(mu, nu)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        move = [float((r.T[0] - x[:, None])[sup].abs().mean()), float((r.T[1] - x[None, :])[sup].abs().mean())]
+        row = {"power": list(power), "iters": r.iters, "seconds": dt, "ms_per_iter": dt / max(r.iters, 1) * 1e3,
+               "dual": r.dual, "gap": r.gap, "mean_abs_motion_per_axis": move}
+        if power == (1.1, 3.0):
+            row["abs_error_vs_1_24"] = abs(r.dual - 1.0 / 24.0)
+        rows.append(row)
+        out = torch.empty_like(mu)
+        for _ in range(2):
+            plan.ctransform(r.phi, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            plan.ctransform(r.phi, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ct_ms["%g,%g" % power] = e0.elapsed_time(e1) / 10
+    return {"workload": "two discs to two crossing discs (Section 4.3, general costs), %d^2, float32" % n,
+            "runs": rows, "ctransform_ms": ct_ms}
+
+
 def cpu_baseline(n):
     """The float64 oracle, timed on a bounded sample of one iteration at the
     same grid: 64 lines of each c-transform pass (scaled to all lines), one
@@ -438,6 +484,8 @@ def main():
         out["interp_c2"] = interp_leg(2000, 1e-5, max(2, args.interp_frames))
     if not args.no_ga:
         out["bfm_vs_ga"] = ga_leg(40, args.ga_cap)
+    if not args.no_pcost:
+        out["pcost_crossing_discs"] = pcost_leg(args.pcost_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))

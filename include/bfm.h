@@ -79,6 +79,13 @@ typedef struct {
     double beta1, beta2, alpha1, alpha2;
     int32_t check_every;   /* iterations enqueued between host reads of the stop flag (>= 1) */
     int32_t method;        /* bfm_method; default BFM_METHOD_BFM */
+    double power[3];       /* cost exponent per axis, 1.05 <= p <= 8 (default 2: the quadratic cost).
+                            * The cost is c(x, y) = sum_a |x_a - y_a|^p_a / p_a (Section 4.3,
+                            * eq. p_costs); p_a = 2 on every axis is |x - y|^2 / 2.  An axis with
+                            * p_a != 2 takes the monotone divide-and-conquer c-transform of
+                            * Section 4.1 (O(n log n) per line) instead of the convex-hull one, and
+                            * the map becomes T = x - (grad h)^{-1}(grad phi^c), component a being
+                            * x_a - sign(g_a) |g_a|^{1/(p_a - 1)}. */
 } bfm_params;
 
 /* Per-solve report (host struct). gap = max(|primal - dual|, G) at the last

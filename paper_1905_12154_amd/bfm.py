@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("sigma0", ctypes.c_double),
                 ("sigma_min", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("alpha1", ctypes.c_double), ("alpha2", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("power", ctypes.c_double * 3)]
 
 
 METHODS = {"bfm": 0, "ga": 1}
@@ -129,7 +129,8 @@ class Plan:
 
     def __init__(self, shape: Sequence[int], dtype=torch.float32, max_iters: int = 60, tol: float = 0.0,
                  sigma0: float = 0.0, sigma_min: float = 0.01, beta1: float = 0.25, beta2: float = 0.75,
-                 alpha1: float = 1.25, alpha2: float = 0.8, check_every: int = 8, method: str = "bfm"):
+                 alpha1: float = 1.25, alpha2: float = 0.8, check_every: int = 8, method: str = "bfm",
+                 power: Optional[Sequence[float]] = None):
         L = lib()
         if method not in METHODS:
             raise ValueError("method must be one of %s" % sorted(METHODS))
@@ -144,6 +145,13 @@ class Plan:
         p.check_every = int(check_every)
         p.method = METHODS[method]
         self.method = method
+        if power is not None:
+            pw = [float(x) for x in power]
+            if len(pw) != len(self.shape):
+                raise ValueError("power needs one exponent per axis (%d), got %d" % (len(self.shape), len(pw)))
+            for a, x in enumerate(pw):
+                p.power[a] = x
+        self.power = tuple(p.power[a] for a in range(len(self.shape)))
         self.params = p
         h = ctypes.c_void_p()
         _check(L.bfm_plan_create(ctypes.byref(p), ctypes.byref(h)))
@@ -331,6 +339,7 @@ _plans = {}
 
 
 def plan_for(shape, dtype, **kw) -> Plan:
+    kw = {k: (tuple(float(x) for x in v) if k == "power" and v is not None else v) for k, v in kw.items()}
     key = (tuple(shape), _dtype_code(dtype), tuple(sorted(kw.items())))
     p = _plans.get(key)
     if p is None:
@@ -345,17 +354,18 @@ def solve(mu: torch.Tensor, nu: torch.Tensor, phi_init=None, return_map=True, **
     return plan_for(mu.shape, mu.dtype, **kw).solve(mu, nu, phi_init=phi_init, return_map=return_map)
 
 
-def ctransform(f: torch.Tensor) -> torch.Tensor:
-    return plan_for(f.shape, f.dtype).ctransform(f)
+def ctransform(f: torch.Tensor, power=None) -> torch.Tensor:
+    """f^c for the quadratic cost, or the power cost of exponents ``power``."""
+    return plan_for(f.shape, f.dtype, power=power).ctransform(f)
 
 
-def interpolate(phi: torch.Tensor, mu: torch.Tensor, times) -> torch.Tensor:
+def interpolate(phi: torch.Tensor, mu: torch.Tensor, times, power=None) -> torch.Tensor:
     """Displacement interpolants between mu and the target of the map of phi."""
-    return plan_for(mu.shape, mu.dtype).interpolate(phi, mu, times)
+    return plan_for(mu.shape, mu.dtype, power=power).interpolate(phi, mu, times)
 
 
-def pushforward(phic: torch.Tensor, mass: torch.Tensor, return_map=True):
-    return plan_for(phic.shape, phic.dtype).pushforward(phic, mass, return_map=return_map)
+def pushforward(phic: torch.Tensor, mass: torch.Tensor, return_map=True, power=None):
+    return plan_for(phic.shape, phic.dtype, power=power).pushforward(phic, mass, return_map=return_map)
 
 
 def poisson_neumann(f: torch.Tensor):

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libbfm.so")
 
-SOURCES = ["ctransform.hip", "dct.hip", "pushforward.hip", "reduce.hip", "solver.hip"]
+SOURCES = ["ctransform.hip", "ctransform_dc.hip", "dct.hip", "pushforward.hip", "reduce.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -112,6 +112,7 @@ struct Grid {
     long long stride[3];
     long long N;
     double vol;    // cell volume
+    double pw[3];  // cost exponent per axis, h_a(z) = |z|^pw / pw (eq. p_costs); 2 = quadratic
 };
 
 }  // namespace bfm

@@ -737,7 +737,7 @@ template <typename T>
 bool ct_blocked_applies(const Grid &g, const void *in, const void *mid, const void *out, const CtCfg *cfg)
 {
     const CtCfg c0 = cfg != nullptr ? cfg[0] : CtCfg{}, c1 = cfg != nullptr ? cfg[1] : CtCfg{};
-    return g.ndim == 2 && (g.n[1] & 3) == 0 && ct_uses_persistent<T>(g.n[0], g.n[1], in, mid, c0) &&
+    return g.ndim == 2 && grid_quadratic(g) && (g.n[1] & 3) == 0 && ct_uses_persistent<T>(g.n[0], g.n[1], in, mid, c0) &&
            ct_shape(g.n[0], true, sizeof(T), c0).lpb == 4 && ct_uses_persistent<T>(g.n[1], 1, mid, out, c1);
 }
 
@@ -775,9 +775,12 @@ hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *d
         const int n = g.n[a];
         const int inner = (int)g.stride[a];
         const long long nlines = g.N / n;
-        hipError_t e = launch_ct_axis<T>(a == g.ndim - 1 ? in : out, out, n, inner, nlines,
-                                         a == g.ndim - 1 ? T(-1) : T(1), done, stream,
-                                         cfg != nullptr ? cfg[a] : CtCfg{});
+        const T *src = a == g.ndim - 1 ? in : out;
+        const T sgn = a == g.ndim - 1 ? T(-1) : T(1);
+        hipError_t e = g.pw[a] != 2.0
+                           ? launch_ct_dc<T>(src, out, n, inner, nlines, sgn, g.pw[a], done, stream)
+                           : launch_ct_axis<T>(src, out, n, inner, nlines, sgn, done, stream,
+                                               cfg != nullptr ? cfg[a] : CtCfg{});
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -40,6 +40,17 @@ template <typename T>
 hipError_t launch_ct_axis(const T *in, T *out, int n, int inner, long long nlines, T sgn,
                           const int32_t *done, hipStream_t stream, CtCfg cfg = CtCfg{});
 int ct_threads_per_line(int n);
+// One axis of the c-transform for the power cost |z|^p / p, p != 2
+// (ctransform_dc.hip): out = min_j |i - j|^p h^p / p + sgn * in_j per line.
+template <typename T>
+hipError_t launch_ct_dc(const T *in, T *out, int n, int inner, long long nlines, T sgn, double p,
+                        const int32_t *done, hipStream_t stream);
+// true when every axis of the grid has the quadratic cost
+inline bool grid_quadratic(const Grid &g) {
+    for (int a = 0; a < g.ndim; ++a)
+        if (g.pw[a] != 2.0) return false;
+    return true;
+}
 template <typename T> size_t ct_smem_bytes(int n, int tpl, int lpb);
 
 // DCT Poisson (dct.hip)

@@ -10,8 +10,12 @@
 //   * T#mu with piecewise-multilinear test functions: the mass of cell x is
 //     split over the 2^d cell centres around T(x) with the multilinear
 //     weights (exact mass conservation up to rounding).
-// Fused float64 partial sums: sum mu |x - T|^2 / 2 (primal cost of the map)
-// and sum mu phi^c (the second term of J).  With tmix != 1 the map is the
+// For the power cost of eq. p_costs, h_a(z) = |z|^{p_a} / p_a, the inverse
+// of h_a' is g -> sign(g) |g|^{1/(p_a - 1)}, so component a of the map is
+// x_a - sign(g_a) |g_a|^{1/(p_a - 1)} with g = grad phi^c (GEN kernels).
+// Fused float64 partial sums: sum mu c(x, T(x)) (primal cost of the map;
+// |x - T|^2 / 2 for the quadratic cost) and sum mu phi^c (the second term
+// of J).  With tmix != 1 the map is the
 // displacement interpolant S_t(x) = t T(x) + (1 - t) x (Section 4.3,
 // optimal transport of images), t = tmix.
 //
@@ -80,7 +84,14 @@ __device__ __forceinline__ void box_deposit(T *box, int key, T w)
 
 // Persistent workgroups walk the tiles in a grid-stride loop; a tile without
 // mass is skipped after one vote.  Partial sums are one per workgroup.
-template <typename T, int D>
+template <typename T> __device__ __forceinline__ T tpow(T x, T y) {
+    if constexpr (sizeof(T) == 4)
+        return powf(x, y);
+    else
+        return pow(x, y);
+}
+
+template <typename T, int D, bool GEN>
 __global__ void __launch_bounds__(kRedBlock)
 splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
              T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
@@ -94,8 +105,13 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
     __shared__ int bnd[2][2 * D];   // box bounds, alternating between consecutive tiles with mass
 
     int ntile[D];
+    T pw[D], ex[D];   // exponent p_a of the cost and 1 / (p_a - 1)
 #pragma unroll
-    for (int a = 0; a < D; ++a) ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
+    for (int a = 0; a < D; ++a) {
+        ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
+        pw[a] = T(g.pw[a]);
+        ex[a] = T(1.0 / (g.pw[a] - 1.0));
+    }
     double accP = 0.0, accJ = 0.0;
     for (int e = threadIdx.x; e < kBoxCap; e += kRedBlock) box[e] = T(0);
     if (threadIdx.x < 2 * D) {
@@ -178,10 +194,16 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                     d = (pc[id + str] - pc[id - str]) * (T(0.5) * fn);
                 const T x = (T(i) + T(0.5)) / fn;
                 const T lo_t = T(0.5) / fn;
+                if constexpr (GEN) {
+                    if (pw[a] != T(2)) d = copysign(tpow(fabs(d), ex[a]), d);
+                }
                 T t = fmin(fmax(x - d, lo_t), T(1) - lo_t);
                 if (tmix != T(1)) t = x + tmix * (t - x);   // displacement interpolation: t T(x) + (1 - t) x
                 if (Tout != nullptr) Tout[(long long)a * g.N + id] = t;
-                sq += (x - t) * (x - t);
+                if constexpr (GEN)
+                    sq += pw[a] == T(2) ? T(0.5) * (x - t) * (x - t) : tpow(fabs(x - t), pw[a]) / pw[a];
+                else
+                    sq += (x - t) * (x - t);
                 const T qq = t * fn - T(0.5);
                 int i0 = (int)floor(qq);
                 i0 = min(max(i0, 0), n - 2);
@@ -191,7 +213,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             }
             base[q] = b;
             if (s[q] != T(0) && rho != nullptr) {
-                accP += (double)s[q] * 0.5 * (double)sq;
+                accP += (double)s[q] * (GEN ? 1.0 : 0.5) * (double)sq;
                 accJ += (double)s[q] * (double)p0;
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
@@ -307,14 +329,21 @@ hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tou
                         double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream, T tmix)
 {
     const long long nb = splat_blocks(g), nt = splat_ntiles(g);
-    if (g.ndim == 2)
-        hipLaunchKernelGGL((splat_kernel<T, 2>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
-                           rho, Tout, part_primal, part_pcsrc, done, tmix);
+    const bool gen = !grid_quadratic(g);
+#define BFM_SPLAT(D_, G_)                                                                                        \
+    hipLaunchKernelGGL((splat_kernel<T, D_, G_>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src, \
+                       rho, Tout, part_primal, part_pcsrc, done, tmix)
+    if (g.ndim == 2 && !gen)
+        BFM_SPLAT(2, false);
+    else if (g.ndim == 2)
+        BFM_SPLAT(2, true);
+    else if (g.ndim == 3 && !gen)
+        BFM_SPLAT(3, false);
     else if (g.ndim == 3)
-        hipLaunchKernelGGL((splat_kernel<T, 3>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src,
-                           rho, Tout, part_primal, part_pcsrc, done, tmix);
+        BFM_SPLAT(3, true);
     else
         return hipErrorInvalidValue;
+#undef BFM_SPLAT
     return hipGetLastError();
 }
 

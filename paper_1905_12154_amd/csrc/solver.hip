@@ -109,6 +109,9 @@ static bfm_status check_params(const bfm_params *p)
     if (p->check_every < 1) return fail(BFM_EINVAL, "check_every must be >= 1");
     if (p->method != BFM_METHOD_BFM && p->method != BFM_METHOD_GA)
         return fail(BFM_EINVAL, "method must be BFM_METHOD_BFM or BFM_METHOD_GA (got %d)", p->method);
+    for (int a = 0; a < p->ndim; ++a)
+        if (!(p->power[a] >= 1.05 && p->power[a] <= 8.0))
+            return fail(BFM_EINVAL, "power[%d] = %g: the cost exponent must lie in [1.05, 8]", a, p->power[a]);
     return BFM_OK;
 }
 
@@ -129,6 +132,7 @@ extern "C" bfm_status bfm_params_init(bfm_params *p, int32_t ndim, const int32_t
     p->alpha2 = 0.8;
     p->check_every = 8;
     p->method = BFM_METHOD_BFM;
+    p->power[0] = p->power[1] = p->power[2] = 2.0;
     return check_params(p);
 }
 
@@ -193,6 +197,7 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     for (int a = p->ndim; a < 3; ++a) g.stride[a] = 0;
     g.vol = 1.0;
     for (int a = 0; a < p->ndim; ++a) g.vol /= g.n[a];
+    for (int a = 0; a < 3; ++a) g.pw[a] = a < p->ndim ? p->power[a] : 2.0;
     for (int a = 0; a < p->ndim; ++a) {
         AxisPlan &ap = P->ax[a];
         ap.n = g.n[a];
@@ -973,6 +978,15 @@ extern "C" bfm_status bfm_ctransform_axis(bfm_plan plan, int32_t axis, int32_t s
     const Grid &g = plan->g;
     hipStream_t s = (hipStream_t)stream;
     const int n = g.n[axis], inner = (int)g.stride[axis];
+    if (g.pw[axis] != 2.0) {
+        if (plan->prm.dtype == BFM_F64)
+            HIP_TRY(launch_ct_dc<double>((const double *)in, (double *)out, n, inner, g.N / n, (double)sign,
+                                         g.pw[axis], nullptr, s));
+        else
+            HIP_TRY(launch_ct_dc<float>((const float *)in, (float *)out, n, inner, g.N / n, (float)sign, g.pw[axis],
+                                        nullptr, s));
+        return BFM_OK;
+    }
     if (plan->prm.dtype == BFM_F64)
         HIP_TRY(launch_ct_axis<double>((const double *)in, (double *)out, n, inner, g.N / n, (double)sign, nullptr,
                                        s, plan->ct_cfg[axis]));

@@ -103,6 +103,21 @@ def test_workspace_size_and_errors_before_launch():
     assert "NULL" in L.bfm_last_error().decode()
 
 
+@pytest.mark.parametrize("value", [1.0, 1.04, 8.5, float("nan"), float("inf")])
+def test_bad_cost_exponent_rejected(value):
+    st, p = _params((32, 32))
+    assert tuple(p.power) == (2.0, 2.0, 2.0)
+    p.power[1] = value
+    h = ctypes.c_void_p()
+    assert bfm.lib().bfm_plan_create(ctypes.byref(p), ctypes.byref(h)) == bfm.BFM_EINVAL
+    assert "power[1]" in bfm.lib().bfm_last_error().decode()
+    # the exponent of an axis beyond ndim is not read
+    st, p = _params((32, 32))
+    p.power[2] = value
+    assert bfm.lib().bfm_plan_create(ctypes.byref(p), ctypes.byref(h)) == bfm.BFM_OK
+    bfm.lib().bfm_plan_destroy(h)
+
+
 def test_plan_python_validation():
     plan = bfm.Plan((32, 32))
     with pytest.raises(TypeError):

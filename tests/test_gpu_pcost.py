@@ -1,0 +1,191 @@
+"""Separable power costs c(x, y) = sum_a |x_a - y_a|^{p_a} / p_a (eq. p_costs)
+on the HIP path against the float64 oracle.
+
+The divide-and-conquer c-transform must give the exact discrete minimum:
+float64 to 1e-13 of the field's scale, float32 to 2e-6 (a few float32 ulps; a
+different minimiser among nearly tied ones changes the value only at
+rounding level).  The map component x_a - sign(g)|g|^{1/(p_a - 1)} has an
+unbounded derivative at g = 0 when p_a > 2, so map parity is held at 1e-7
+cells there (rounding of g near 0 is amplified), 1e-12 otherwise."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfm as ob
+from paper_1905_12154_amd import bfm, workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rand_field(shape, seed, kind):
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        return rng.normal(scale=0.2, size=shape)
+    if kind == "smooth":   # a potential plus noise: long brackets in few rows
+        xs = ob.centres(shape)
+        return sum(0.3 * x * x - 0.2 * x for x in xs) + 0.01 * rng.normal(size=shape)
+    if kind == "flat":     # many exact ties
+        return np.round(rng.normal(scale=0.05, size=shape), 2)
+    raise ValueError(kind)
+
+
+CT_CASES = [((4, 4), (1.5, 3.0)), ((6, 12), (1.1, 2.0)), ((64, 64), (3.0, 1.1)), ((96, 48), (1.5, 2.5)),
+            ((1024, 8), (1.25, 4.0)), ((8, 1024), (2.0, 1.3)), ((4096, 4), (1.5, 2.0)), ((4, 4096), (2.0, 3.0)),
+            ((8, 6, 4), (1.5, 2.0, 3.0)), ((24, 32, 18), (2.5, 1.2, 2.0)), ((12, 96, 16), (1.05, 8.0, 1.7))]
+
+
+@pytest.mark.parametrize("shape,power", CT_CASES)
+@pytest.mark.parametrize("kind", ["normal", "smooth", "flat"])
+def test_ctransform_f64_matches_oracle(shape, power, kind):
+    f = rand_field(shape, 3, kind)
+    ref = ob.ctransform(f, power)
+    out = host(bfm.ctransform(cuda(f), power=power))
+    assert np.max(np.abs(out - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("shape,power", [((64, 64), (3.0, 1.1)), ((384, 128), (1.5, 2.5)), ((4096, 16), (1.3, 2.0)),
+                                         ((24, 32, 18), (2.5, 1.2, 2.0))])
+def test_ctransform_f32(shape, power):
+    f = rand_field(shape, 4, "smooth")
+    ref = ob.ctransform(f.astype(np.float32).astype(np.float64), power)
+    out = host(bfm.ctransform(cuda(f, torch.float32), power=power))
+    assert np.max(np.abs(out - ref)) <= 2e-6 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_ctransform_axis_matches_line_minimum():
+    shape, power = (48, 36), (1.5, 3.0)
+    f = rand_field(shape, 5, "normal")
+    plan = bfm.plan_for(shape, torch.float64, power=power)
+    for axis in (0, 1):
+        out = host(plan.ctransform_axis(cuda(f), axis, sign=1))
+        ref = ob.line_min_p(f, axis, power[axis])
+        assert np.max(np.abs(out - ref)) <= 1e-13
+
+
+def test_power_two_axis_uses_the_quadratic_transform_exactly():
+    # an axis with p = 2 next to one with p != 2: still the exact minimum
+    f = rand_field((96, 64), 6, "normal")
+    out = host(bfm.ctransform(cuda(f), power=(2.0, 1.5)))
+    assert np.max(np.abs(out - ob.ctransform(f, (2.0, 1.5)))) <= 1e-13
+
+
+def _map_case(shape, seed):
+    rng = np.random.default_rng(seed)
+    xs = ob.centres(shape)
+    pc = sum(-0.15 * x * x + 0.05 * x for x in xs) + 0.004 * rng.normal(size=shape)
+    mass = rng.uniform(0.0, 2.0, size=shape)
+    mass[rng.uniform(size=shape) < 0.3] = 0.0
+    return pc, mass
+
+
+@pytest.mark.parametrize("shape,power", [((64, 64), (1.5, 3.0)), ((96, 384), (1.1, 2.0)),
+                                         ((24, 32, 18), (2.5, 1.3, 2.0))])
+def test_pushforward_f64_matches_oracle(shape, power):
+    pc, mass = _map_case(shape, 7)
+    rho, T, P = bfm.pushforward(cuda(pc), cuda(mass), power=power)
+    Tr = ob.transport_map(pc, power)
+    for a in range(len(shape)):
+        tol = 1e-7 if power[a] > 2.0 else 1e-12
+        assert np.max(np.abs(host(T[a]) - Tr[a])) * shape[a] <= tol
+    # deposit the oracle's mass through the GPU's own map: the deposition is
+    # then compared exactly, the map separately above
+    rr = ob.pushforward(mass, [host(T[a]) for a in range(len(shape))])
+    assert np.max(np.abs(host(rho) - rr)) <= 1e-12 * np.max(rr)
+    Pr = ob.primal_cost(mass, Tr, power)
+    assert abs(P - Pr) <= 1e-9 * abs(Pr)
+
+
+def _solve_both(mu, nu, dtype, iters, power, **kw):
+    plan = bfm.plan_for(mu.shape, dtype, max_iters=iters, power=power, **kw)
+    r = plan.solve(cuda(mu, dtype), cuda(nu, dtype))
+    tr = plan.trace(torch.device(DEV))
+    o = ob.solve(mu, nu, ob.Params(max_iters=iters, powers=power))
+    return r, tr, o
+
+
+def test_crossing_discs_move_along_one_axis():
+    # Section 4.3 (general costs): exponents 3 and 1.1 -> cost 1/24, no motion
+    # along the second axis
+    mu, nu = wl.crossing_discs(128)
+    r, tr, o = _solve_both(mu, nu, torch.float64, 20, (3.0, 1.1))
+    assert min(abs(e["dual"] - 1.0 / 24.0) for e in tr) <= 1e-12
+    for g, e in zip(tr, o.trace):
+        assert abs(g["dual"] - e["dual"]) <= 1e-9
+    xs = ob.centres(mu.shape)
+    sup = mu > 0
+    assert np.max(np.abs(host(r.T[1]) - xs[1])[sup]) <= 0.25 / 128
+
+
+@pytest.mark.parametrize("shape,shift,power", [((48, 48), (7, -5), (1.5, 3.0)), ((36, 54), (-6, 9), (3.0, 1.5))])
+def test_translation_exact_cost(shape, shift, power):
+    mu, nu = wl.translated_pair(shape, shift, np.random.default_rng(11), rmin=0.06, rmax=0.1)
+    r, tr, o = _solve_both(mu, nu, torch.float64, 40, power)
+    exact = sum(abs(s / n) ** p / p for s, n, p in zip(shift, shape, power))
+    assert min(abs(e["dual"] - exact) for e in tr) <= 1e-11
+    assert all(e["dual"] <= exact + 1e-12 for e in tr)
+
+
+@pytest.mark.parametrize("shape,power,iters", [((64, 64), (1.5, 2.5), 25), ((96, 384), (2.0, 1.3), 10),
+                                               ((16, 24, 18), (1.5, 2.0, 3.0), 8)])
+def test_solve_parity_f64(shape, power, iters):
+    rng = np.random.default_rng(21)
+    mu = wl.random_gaussian_mixture(shape, 3, rng)
+    nu = wl.random_gaussian_mixture(shape, 2, rng)
+    r, tr, o = _solve_both(mu, nu, torch.float64, iters, power)
+    assert r.iters == o.iters == iters
+    for g, e in zip(tr, o.trace):
+        assert abs(g["dual"] - e["dual"]) <= 1e-9
+        assert g["sigma"] == pytest.approx(e["sigma"], rel=1e-9)
+    for a in range(len(shape)):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * shape[a] <= 1e-3
+
+
+def test_solve_f32_error_vs_oracle():
+    mu, nu = wl.config_c1()
+    power = (1.5, 2.5)
+    r = bfm.solve(cuda(mu, torch.float32), cuda(nu, torch.float32), max_iters=30, power=power)
+    o = ob.solve(mu, nu, ob.Params(max_iters=30, powers=power))
+    assert abs(r.dual - o.dual) <= 1e-4 * abs(o.dual)
+
+
+def test_gradient_ascent_with_power_cost():
+    mu, nu = wl.config_c1()
+    power = (3.0, 1.5)
+    plan = bfm.plan_for(mu.shape, torch.float64, max_iters=15, power=power, method="ga")
+    r = plan.solve(cuda(mu), cuda(nu))
+    tr = plan.trace(torch.device(DEV))
+    o = ob.solve_ga(mu, nu, ob.Params(max_iters=15, powers=power))
+    for g, e in zip(tr, o.trace):
+        assert abs(g["dual"] - e["dual"]) <= 1e-9
+    assert np.max(np.abs(host(r.psi) - o.psi)) <= 1e-6
+
+
+def test_interpolant_with_power_cost():
+    shape, power = (64, 48), (1.5, 3.0)
+    pc, mass = _map_case(shape, 8)
+    mass = wl.normalise(mass)
+    # the interpolation entry point takes phi and transforms it itself
+    phi = ob.ctransform(pc, power)   # c-concave potential whose transform is pc^cc
+    frames = bfm.interpolate(cuda(phi), cuda(mass), [0.0, 0.3, 1.0], power=power)
+    pcc = ob.ctransform(phi, power)
+    for k, t in enumerate((0.0, 0.3, 1.0)):
+        ref = ob.displacement_interpolant(mass, pcc, t, power)
+        assert np.max(np.abs(host(frames[k]) - ref)) <= 1e-5 * np.max(ref)
+
+
+def test_power_out_of_range_rejected():
+    for bad in ((1.0, 2.0), (2.0, 9.0), (float("nan"), 2.0)):
+        with pytest.raises(bfm.BFMError):
+            bfm.Plan((32, 32), torch.float64, power=bad)
+    with pytest.raises(ValueError):
+        bfm.Plan((32, 32), torch.float64, power=(2.0,))
