@@ -374,7 +374,8 @@ def poisson_neumann(f: torch.Tensor):
 
 def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_iters: int = 100,
                   tol: float = 0.0, iters_per_graph: int = 8, return_map: bool = False,
-                  workspaces: Optional[List[torch.Tensor]] = None, method: str = "bfm") -> List[SolveResult]:
+                  workspaces: Optional[List[torch.Tensor]] = None, method: str = "bfm",
+                  power: Optional[Sequence[float]] = None) -> List[SolveResult]:
     """Solve many independent problems together (``bfm_solve_batched``): one
     HIP graph replay advances every problem by ``iters_per_graph`` iterations.
     Problems may have different shapes; all share dtype and ``max_iters``."""
@@ -382,7 +383,7 @@ def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_
     if n != len(nus) or n == 0:
         raise ValueError("need the same positive number of mu and nu tensors")
     dev = mus[0].device
-    plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol, method=method) for m in mus]
+    plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol, method=method, power=power) for m in mus]
     mus = [p._field(m, "mu[%d]" % i) for i, (p, m) in enumerate(zip(plans, mus))]
     nus = [p._field(v, "nu[%d]" % i) for i, (p, v) in enumerate(zip(plans, nus))]
     phis = [torch.empty_like(m) for m in mus]

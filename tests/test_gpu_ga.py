@@ -136,3 +136,18 @@ def test_ga_batched_matches_single():
         assert rb.iters == 20
         assert abs(rb.dual - o.dual) <= 1e-10
         assert np.max(np.abs(host(rb.phi) - o.phi)) <= 1e-6
+
+
+def test_ga_full_size_two_discs_properties():
+    """The comparison leg's size (1024^2 float64): at every iteration the dual
+    stays below the exact cost 1/4 (weak duality) and the double transform
+    does not lower it; the error reaches 1e-4 within the cap."""
+    mu, nu = wl.two_discs(1024)
+    plan = bfm.plan_for(mu.shape, torch.float64, max_iters=80, method="ga")
+    plan.solve(cuda(mu), cuda(nu), return_map=False)
+    tr = plan.trace(torch.device(DEV))
+    assert len(tr) == 81
+    assert all(e["dual"] <= 0.25 + 1e-12 for e in tr)
+    for k in range(len(tr) - 1):
+        assert tr[k]["J_half"] <= tr[k + 1]["dual"] + 1e-12
+    assert min(abs(e["dual"] - 0.25) for e in tr) < 1e-4

@@ -65,3 +65,27 @@ def test_interpolate_argument_errors():
         with pytest.raises(bfm.BFMError) as e:
             plan.interpolate(x, x, bad)
         assert e.value.status == bfm.BFM_EINVAL
+
+
+def test_interpolant_full_size_c2_properties():
+    """The interpolation leg's workload (c2, 1024^2 float32, solved to gap
+    1e-5): every frame conserves mass, t = 0 gives mu, t = 1 the method's
+    pushforward, and the frames at sampled cells match the oracle's
+    deposition of the same map (the map itself from the GPU potential)."""
+    mu, nu = wl.config_c2()
+    tmu, tnu = cuda(mu, torch.float32), cuda(nu, torch.float32)
+    r = bfm.solve(tmu, tnu, max_iters=200, tol=1e-5)
+    assert r.converged
+    frames = bfm.interpolate(r.phi, tmu, TIMES)
+    mass = float(tmu.double().sum())
+    for k in range(len(TIMES)):
+        assert abs(float(frames[k].double().sum()) - mass) <= 1e-5 * mass
+    assert float((frames[0] - tmu).abs().max()) <= 1e-5 * float(tmu.max())
+    pc = bfm.ctransform(r.phi)
+    rho1, T, _ = bfm.pushforward(pc, tmu)
+    assert float((frames[-1] - rho1).abs().max()) <= 1e-5 * float(rho1.abs().max())
+    # t = 1/2 through the oracle's deposition of S_t built from the GPU map
+    xs = ob.centres(mu.shape)
+    S = [0.5 * host(T[a]) + 0.5 * xs[a] for a in range(2)]
+    ref = ob.pushforward(mu.astype(np.float32).astype(np.float64), S)
+    assert np.max(np.abs(host(frames[2]) - ref)) <= 1e-4 * ref.max()

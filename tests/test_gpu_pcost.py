@@ -189,3 +189,52 @@ def test_power_out_of_range_rejected():
             bfm.Plan((32, 32), torch.float64, power=bad)
     with pytest.raises(ValueError):
         bfm.Plan((32, 32), torch.float64, power=(2.0,))
+
+
+def test_batched_with_power_costs_matches_single():
+    rng = np.random.default_rng(31)
+    shapes = [(64, 64), (48, 96)]
+    pairs = [(wl.random_gaussian_mixture(s, 2, rng), wl.random_gaussian_mixture(s, 3, rng)) for s in shapes]
+    power = (1.5, 2.5)
+    singles = [bfm.solve(cuda(m), cuda(v), max_iters=12, power=power) for m, v in pairs]
+    rs = bfm.solve_batched([cuda(m) for m, _ in pairs], [cuda(v) for _, v in pairs], max_iters=12,
+                           iters_per_graph=4, power=power)
+    for (m, v), rb, r1 in zip(pairs, rs, singles):
+        assert rb.iters == r1.iters == 12
+        assert abs(rb.dual - r1.dual) <= 1e-12
+        o = ob.solve(m, v, ob.Params(max_iters=12, powers=power))
+        assert abs(rb.dual - o.dual) <= 1e-9
+
+
+def test_full_size_ctransform_sampled_1024():
+    """The bench's power-cost workload size (1024^2 float32): the c-transform
+    at sampled points against the definition over all 1M grid points y."""
+    n = 1024
+    power = (1.1, 3.0)
+    xs = ob.centres((n, n))
+    f = (0.2 * xs[0] ** 2 - 0.1 * xs[1] + 0.05 * np.sin(9 * xs[0] * xs[1])).astype(np.float32)
+    got = host(bfm.ctransform(cuda(f, torch.float32), power=power))
+    y = (np.arange(n) + 0.5) / n
+    fd = f.astype(np.float64)
+    rng = np.random.default_rng(1)
+    for _ in range(24):
+        i, j = rng.integers(0, n, size=2)
+        c = (np.abs((i + 0.5) / n - y)[:, None] ** power[0] / power[0]
+             + np.abs((j + 0.5) / n - y)[None, :] ** power[1] / power[1])
+        ref = np.min(c - fd)
+        assert abs(got[i, j] - ref) <= 2e-6, (i, j)
+
+
+def test_full_size_crossing_discs_f32():
+    """The bench leg (1024^2 float32, exponents (1.1, 3)): the dual stays below
+    the exact cost 1/24 up to float32 rounding and reaches it; no motion along
+    the axis of exponent 1.1."""
+    mu, nu = wl.crossing_discs(1024)
+    plan = bfm.plan_for(mu.shape, torch.float32, max_iters=30, power=(1.1, 3.0))
+    r = plan.solve(cuda(mu, torch.float32), cuda(nu, torch.float32))
+    tr = plan.trace(torch.device(DEV))
+    assert all(e["dual"] <= 1.0 / 24.0 + 1e-7 for e in tr)
+    assert abs(r.dual - 1.0 / 24.0) <= 1e-7
+    xs = (np.arange(1024) + 0.5) / 1024
+    sup = mu > 0
+    assert np.max(np.abs(host(r.T[0]) - xs[:, None])[sup]) <= 0.25 / 1024
