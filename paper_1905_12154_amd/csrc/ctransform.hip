@@ -153,7 +153,12 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     }
 
     // 3. merge neighbouring hulls, doubling the group width each round; a
-    //    group of 2r <= 64 lanes lies in one wave and synchronises only it
+    //    group of 2r <= 64 lanes lies in one wave and synchronises only it.
+    //    The merges and the markers below are short chains of dependent LDS
+    //    reads on few lanes, while other workgroups on the CU stream through
+    //    their lines: these waves take issue priority until the markers are
+    //    placed.
+    __builtin_amdgcn_s_setprio(3);
     for (int r = 1; r < tpl; r <<= 1) {
         if (2 * r <= kWave) wave_sync();
         else __syncthreads();
@@ -228,6 +233,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
         if (st[c] < n) atomicMax(&mk[padi(st[c])], j0 + c);
     line_sync(tpl);
 
+    __builtin_amdgcn_s_setprio(0);
     // prefix maximum of the markers along the line
     int loc[C];
     int m = -1;
