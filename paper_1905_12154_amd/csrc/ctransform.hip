@@ -113,7 +113,9 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     const T n2 = T(n) * T(n);
     // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
     //    entries live in registers (u holds the lane's values), so only pops
-    //    read LDS
+    //    read LDS.  Each push also links the element below it forward
+    //    (a later push over the same element overwrites a popped successor),
+    //    so the forward links of the final stack need no second walk.
     if (j0 < j1) {
         int top = j0, a = -1;
         T utop = u[0], ua = T(0);
@@ -131,20 +133,14 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                     if (a >= 0) ua = v[padi(a)];
                 }
                 pv[padi(j)] = (short)top;
+                nx[padi(top)] = (short)j;
                 a = top;
                 ua = utop;
                 top = j;
                 utop = uj;
             }
         }
-        int k = top;
-        nx[padi(k)] = kNone;
-        while (true) {
-            const int p = pv[padi(k)];
-            if (p < 0) break;
-            nx[padi(p)] = (short)k;
-            k = p;
-        }
+        nx[padi(top)] = kNone;
         GH[t] = j0;
         GT[t] = top;
     } else {
