@@ -211,7 +211,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
             if (p == kNone) {
                 st[c] = 0;
             } else if (p >= 0) {
-                T s = T(0.5) * T(j + p) + n2 * (v[padi(j)] - v[padi(p)]) / T(j - p);
+                T s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) / T(j - p);
                 s = fmin(fmax(s, T(-1)), T(n));
                 const int si = (int)ceil(s);
                 st[c] = si < 0 ? 0 : si;
