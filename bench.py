@@ -401,7 +401,7 @@ def pmc_leg(n, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -46,7 +46,7 @@ typedef enum {
     BFM_EDEVICE = 2,       /* a HIP call failed (launch, copy, synchronise) */
     BFM_ENUMERIC = 3,      /* a non-finite value appeared in the device state */
     BFM_EWORKSPACE = 4,    /* workspace pointer null, misaligned or too small */
-    BFM_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+    BFM_EUNSUPPORTED = 5   /* valid request outside what the library implements */
 } bfm_status;
 
 typedef enum { BFM_F32 = 0, BFM_F64 = 1 } bfm_dtype;
