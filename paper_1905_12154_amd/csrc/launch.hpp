@@ -70,9 +70,17 @@ hipError_t launch_dct_fused(T *X, const AxisPlan &ap0, long long N, int nA, int 
 long long dct_fused_parts(int n0, long long N, size_t esz);
 
 // map, pushforward, reductions, controller (pushforward.hip, reduce.hip)
+// tiles (nullable): count followed by the indices of the source tiles with
+// mass, from launch_tile_list; only those tiles are deposited
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream, T tmix = T(1));
+                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream, T tmix = T(1),
+                        const int *tiles = nullptr);
+// list of the deposition tiles of src that hold mass (flags: splat_tile_count
+// ints of scratch; list: splat_tile_count + 1 ints)
+template <typename T>
+hipError_t launch_tile_list(const Grid &g, const T *src, int *flags, int *list, hipStream_t stream);
+long long splat_tile_count(const Grid &g);
 template <typename T>
 hipError_t launch_dot2(const T *a1, const T *b1, const T *a2, const T *b2, long long N, double *part1,
                        double *part2, int nblocks, const int32_t *done, hipStream_t stream);

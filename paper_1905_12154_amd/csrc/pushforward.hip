@@ -83,7 +83,10 @@ __device__ __forceinline__ void box_deposit(T *box, int key, T w)
 }
 
 // Persistent workgroups walk the tiles in a grid-stride loop; a tile without
-// mass is skipped after one vote.  Partial sums are one per workgroup.
+// mass is skipped after one vote.  With `tiles` (a count followed by tile
+// indices, as tile_list_kernel writes them) only the listed tiles are walked:
+// the sources of a solve do not change, so the tiles without mass are found
+// once.  Partial sums are one per workgroup.
 template <typename T> __device__ __forceinline__ T tpow(T x, T y) {
     if constexpr (sizeof(T) == 4)
         return powf(x, y);
@@ -95,7 +98,8 @@ template <typename T, int D, bool GEN>
 __global__ void __launch_bounds__(kRedBlock)
 splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
              T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
-             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done, T tmix)
+             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done, T tmix,
+             const int *__restrict__ tiles)
 {
     if (done != nullptr && *done) return;
     constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
@@ -121,7 +125,9 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
     __syncthreads();
     int kused = 0;   // tiles with mass processed so far by this workgroup
 
-    for (long long tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
+    const long long count = tiles != nullptr ? (long long)tiles[0] : ntiles_total;
+    for (long long k = blockIdx.x; k < count; k += gridDim.x) {
+        const long long tile = tiles != nullptr ? (long long)tiles[1 + k] : k;
         int tc[D];
         long long rem = tile;
 #pragma unroll
@@ -324,15 +330,104 @@ long long splat_blocks(const Grid &g) {
     return t < 2048 ? t : 2048;
 }
 
+long long splat_tile_count(const Grid &g) { return splat_ntiles(g); }
+
+// flags[tile] = 1 when some source cell of the tile holds mass
+template <typename T, int D>
+__global__ void __launch_bounds__(kRedBlock)
+tile_flag_kernel(Grid g, long long ntiles, const T *__restrict__ src, int *__restrict__ flags)
+{
+    constexpr int PER = Tile<D>::cells / kRedBlock;
+    int ntile[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int tc[D];
+        long long rem = tile;
+#pragma unroll
+        for (int a = D - 1; a >= 0; --a) {
+            tc[a] = (int)(rem % ntile[a]);
+            rem /= ntile[a];
+        }
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            int r = threadIdx.x + q * kRedBlock;
+            bool inside = true;
+            long long id = 0;
+#pragma unroll
+            for (int a = D - 1; a >= 0; --a) {
+                const int i = tc[a] * Tile<D>::s[a] + r % Tile<D>::s[a];
+                r /= Tile<D>::s[a];
+                inside = inside && i < g.n[a];
+                id += (long long)i * g.stride[a];
+            }
+            any = any || (inside && src[id] != T(0));
+        }
+        const int f = __syncthreads_or(any);
+        if (threadIdx.x == 0) flags[tile] = f;
+    }
+}
+
+// list[0] = number of flagged tiles, list[1..] = their indices in tile order
+// (one workgroup: contiguous runs of flags per lane and a block scan, so the
+// order, and with it every partial sum of the deposition, is deterministic)
+constexpr int kListBlock = 1024;
+__global__ void __launch_bounds__(kListBlock)
+tile_list_kernel(const int *__restrict__ flags, long long ntiles, int *__restrict__ list)
+{
+    __shared__ int wsum[kListBlock / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const long long per = (ntiles + kListBlock - 1) / kListBlock;
+    const long long b0 = t * per, b1 = b0 + per < ntiles ? b0 + per : ntiles;
+    int cnt = 0;
+    for (long long i = b0; i < b1; ++i) cnt += flags[i] != 0;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int q = 0; q < kListBlock / kWave; ++q) {
+        off += q < w ? wsum[q] : 0;
+        total += wsum[q];
+    }
+    int pos = off + incl - cnt;
+    for (long long i = b0; i < b1; ++i)
+        if (flags[i] != 0) list[1 + pos++] = (int)i;
+    if (t == 0) list[0] = total;
+}
+
+template <typename T>
+hipError_t launch_tile_list(const Grid &g, const T *src, int *flags, int *list, hipStream_t stream)
+{
+    const long long nt = splat_ntiles(g);
+    const long long nb = nt < 4096 ? nt : 4096;
+    if (g.ndim == 2)
+        hipLaunchKernelGGL((tile_flag_kernel<T, 2>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, src, flags);
+    else if (g.ndim == 3)
+        hipLaunchKernelGGL((tile_flag_kernel<T, 3>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, src, flags);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tile_list_kernel, dim3(1), dim3(kListBlock), 0, stream, flags, nt, list);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream, T tmix)
+                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream, T tmix,
+                        const int *tiles)
 {
     const long long nb = splat_blocks(g), nt = splat_ntiles(g);
     const bool gen = !grid_quadratic(g);
 #define BFM_SPLAT(D_, G_)                                                                                        \
     hipLaunchKernelGGL((splat_kernel<T, D_, G_>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src, \
-                       rho, Tout, part_primal, part_pcsrc, done, tmix)
+                       rho, Tout, part_primal, part_pcsrc, done, tmix, tiles)
     if (g.ndim == 2 && !gen)
         BFM_SPLAT(2, false);
     else if (g.ndim == 2)
@@ -348,8 +443,10 @@ hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tou
 }
 
 template hipError_t launch_splat<float>(const Grid &, const float *, const float *, float *, float *, double *,
-                                        double *, int, const int32_t *, hipStream_t, float);
+                                        double *, int, const int32_t *, hipStream_t, float, const int *);
 template hipError_t launch_splat<double>(const Grid &, const double *, const double *, double *, double *,
-                                         double *, double *, int, const int32_t *, hipStream_t, double);
+                                         double *, double *, int, const int32_t *, hipStream_t, double, const int *);
+template hipError_t launch_tile_list<float>(const Grid &, const float *, int *, int *, hipStream_t);
+template hipError_t launch_tile_list<double>(const Grid &, const double *, int *, int *, hipStream_t);
 
 }  // namespace bfm

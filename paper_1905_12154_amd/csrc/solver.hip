@@ -58,6 +58,8 @@ struct bfm_plan_s {
     CtCfg ct_cfg[3];   // c-transform launch shape per axis (autotuned or built-in)
     // workspace layout (byte offsets from the workspace base)
     size_t off_state, off_trace, off_part, off_gpart, off_tables, off_pc, off_rho, off_f, total;
+    size_t off_tiles_mu, off_tiles_nu;   // deposition tiles of mu and nu that hold mass
+    long long ntiles;
     size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
     std::vector<unsigned char> tables;         // host image of the spectral tables
 };
@@ -222,6 +224,9 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     P->gparts = (int)dct_fused_parts(g.n[0], g.N, P->esz);
     P->off_gpart = off;  off = align256(off + sizeof(double) * (size_t)P->gparts);
     P->off_tables = off; off = align256(off + P->tables.size());
+    P->ntiles = splat_tile_count(g);
+    P->off_tiles_mu = off; off = align256(off + sizeof(int) * (size_t)(P->ntiles + 1));
+    P->off_tiles_nu = off; off = align256(off + sizeof(int) * (size_t)(P->ntiles + 1));
     const size_t fb = align256((size_t)g.N * P->esz);
     P->off_pc = off;  off += fb;
     P->off_rho = off; off += fb;
@@ -249,6 +254,7 @@ struct Ws {
     double *gpart;
     unsigned char *tables;
     void *pc, *rho, *f;
+    int *tiles_mu, *tiles_nu;   // filled by solve_begin
     long long slot_len;
     double *slot(int s) const { return part + (size_t)s * slot_len; }
 };
@@ -269,6 +275,8 @@ static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
     w->pc = b + P->off_pc;
     w->rho = b + P->off_rho;
     w->f = b + P->off_f;
+    w->tiles_mu = (int *)(b + P->off_tiles_mu);
+    w->tiles_nu = (int *)(b + P->off_tiles_nu);
     return BFM_OK;
 }
 
@@ -372,8 +380,9 @@ static hipError_t poisson_inverse(bfm_plan P, const Ws &w, T *F, T *out, T *upda
 // head_ct = false takes pc as already holding p^c (gradient ascent, where
 // the previous step left it there).
 template <typename T>
-static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T *tgt, T *q, int head_mode,
-                            int step_mode, bool head_only, bool head_dot, hipStream_t s, bool head_ct = true)
+static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const int *src_tiles, const T *tgt, T *q,
+                            int head_mode, int step_mode, bool head_only, bool head_dot, hipStream_t s,
+                            bool head_ct = true)
 {
     const Grid &g = P->g;
     const int32_t *done = &w.st->done;
@@ -386,7 +395,8 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const T
     if (head_dot &&
         (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
-    if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, done, s)) !=
+    if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, done, s, T(1),
+                             src_tiles)) !=
         hipSuccess)
         return e;
     if ((e = poisson_forward<T>(P, w, tgt, rho, 1, F, done, s)) != hipSuccess) return e;
@@ -436,6 +446,10 @@ static bfm_status solve_begin(bfm_plan P, const T *mu, const T *nu, const T *phi
     HIP_TRY(launch_stats<T>(mu, nu, g.N, w.part, P->slot_len, P->red_blocks, s));
     HIP_TRY(launch_ctrl(w.st, w.part, w.gpart, CTRL_INIT, ctrl_params(P), w.trace, s));
     HIP_TRY(launch_fill<T>((T *)w.rho, g.N, T(0), s));
+    // the deposition walks only the tiles of mu (phi-steps) and nu (psi-steps)
+    // that hold mass; F is free scratch here
+    HIP_TRY(launch_tile_list<T>(g, mu, (int *)w.f, w.tiles_mu, s));
+    HIP_TRY(launch_tile_list<T>(g, nu, (int *)w.f, w.tiles_nu, s));
     if (phi_init != nullptr)
         HIP_TRY(hipMemcpyAsync(phi, phi_init, (size_t)g.N * sizeof(T), hipMemcpyDeviceToDevice, s));
     else
@@ -461,7 +475,8 @@ static hipError_t ga_iteration(bfm_plan P, const Ws &w, const T *mu, const T *nu
     const int32_t *done = &w.st->done;
     T *pc = (T *)w.pc, *F = (T *)w.f;
     hipError_t e;
-    if ((e = half_step<T>(P, w, phi, mu, nu, pc, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, first, s, first)) !=
+    if ((e = half_step<T>(P, w, phi, mu, w.tiles_mu, nu, pc, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, first, s,
+                          first)) !=
         hipSuccess)
         return e;
     int nd = 0;
@@ -490,9 +505,11 @@ static hipError_t enqueue_iterations(bfm_plan P, const Ws &w, const T *mu, const
         return hipSuccess;
     }
     for (int it = it0; it < it0 + count; ++it) {
-        if ((e = half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, it == 0, s)) != hipSuccess)
+        if ((e = half_step<T>(P, w, phi, mu, w.tiles_mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, false, it == 0,
+                              s)) != hipSuccess)
             return e;
-        if ((e = half_step<T>(P, w, psi, nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, false, s)) != hipSuccess)
+        if ((e = half_step<T>(P, w, psi, nu, w.tiles_nu, mu, phi, CTRL_HEAD_PSI, CTRL_STEP_PSI, false, false, s)) !=
+            hipSuccess)
             return e;
     }
     return hipSuccess;
@@ -503,7 +520,7 @@ static hipError_t enqueue_final_head(bfm_plan P, const Ws &w, const T *mu, const
                                      hipStream_t s)
 {
     // gradient ascent keeps phi^c in pc from the last step
-    return half_step<T>(P, w, phi, mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, true, it == 0, s,
+    return half_step<T>(P, w, phi, mu, w.tiles_mu, nu, psi, CTRL_HEAD_PHI, CTRL_STEP_PHI, true, it == 0, s,
                         P->prm.method != BFM_METHOD_GA || it == 0);
 }
 
