@@ -34,9 +34,11 @@
 
 namespace bfm {
 
-// LDS box cells: 8 KB in 2D, 16 KB in 3D (a 3D tile's targets spread over
-// a box that grows with the cube of the local expansion of the map)
-template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 8192) / (int)sizeof(T); }
+// LDS box: 32 KB in 2D, 16 KB in 3D.  A 2D tile's targets overflow the box
+// only where the map expands by more than about 2.8 per axis; the
+// workgroups per CU are set by registers, not by this LDS.  In 3D a larger
+// box was slower.
+template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 32768) / (int)sizeof(T); }
 
 template <int D> struct Tile;
 template <> struct Tile<2> { static constexpr int s[2] = {32, 32}; static constexpr int cells = 1024; };
@@ -175,6 +177,23 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             bmin[a] = 0x7fffffff;
             bmax[a] = -1;
         }
+        // phi^c at every source of the lane and its two neighbours per axis
+        // (the face neighbour outside the grid replaced by the cell itself),
+        // all loaded before any is used so that they are in flight together
+        T pcv[PER][1 + 2 * D];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const bool ok = idx[q] >= 0;
+            const long long id = ok ? idx[q] : 0;
+            pcv[q][0] = pc[id];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int i = ii[q][a];
+                const long long str = g.stride[a];
+                pcv[q][1 + 2 * a] = pc[ok && i + 1 < g.n[a] ? id + str : id];
+                pcv[q][2 + 2 * a] = pc[ok && i > 0 ? id - str : id];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (idx[q] < 0 || (s[q] == T(0) && Tout == nullptr)) {
@@ -182,7 +201,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                 continue;
             }
             const long long id = idx[q];
-            const T p0 = pc[id];
+            const T p0 = pcv[q][0];
             T sq = T(0);
             long long b = 0;
 #pragma unroll
@@ -191,13 +210,14 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
                 const long long str = g.stride[a];
                 const int i = ii[q][a];
                 const T fn = T(n);
+                const T pp = pcv[q][1 + 2 * a], pm = pcv[q][2 + 2 * a];
                 T d;
                 if (i == 0)
-                    d = (pc[id + str] - p0) * fn;
+                    d = (pp - p0) * fn;
                 else if (i == n - 1)
-                    d = (p0 - pc[id - str]) * fn;
+                    d = (p0 - pm) * fn;
                 else
-                    d = (pc[id + str] - pc[id - str]) * (T(0.5) * fn);
+                    d = (pp - pm) * (T(0.5) * fn);
                 const T x = (T(i) + T(0.5)) / fn;
                 const T lo_t = T(0.5) / fn;
                 if constexpr (GEN) {
