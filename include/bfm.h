@@ -192,22 +192,27 @@ bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9);
 bfm_status bfm_interpolate(bfm_plan plan, const void *phi, const void *mu, int32_t ntimes, const double *times,
                            void *rho, void *workspace, size_t ws_bytes, void *stream);
 
-/* Primitive: quadratic-cost c-transform on the grid (Definition of the
- * c-transform; separable evaluation of Section 4.1; per line the Legendre
- * transform on the lower convex hull, eq. legendre / legendre_search):
- *   out(x) = min over grid points y of |x - y|^2 / 2 - in(y).
- * in and out are device fields of N elements; out may equal in. */
+/* Primitive: c-transform on the grid for the plan's cost (Definition of the
+ * c-transform; separable evaluation of Section 4.1):
+ *   out(x) = min over grid points y of c(x, y) - in(y),
+ * c = |x - y|^2 / 2 (per line the Legendre transform on the lower convex
+ * hull, eq. legendre / legendre_search), or with params.power the sum over
+ * axes of |x_a - y_a|^p_a / p_a (axes with p_a != 2 by the monotone divide and
+ * conquer of Section 4.1).  in and out are device fields of N elements; out
+ * may equal in. */
 bfm_status bfm_ctransform(bfm_plan plan, const void *in, void *out, void *workspace,
                           size_t ws_bytes, void *stream);
 
-/* Primitive: map and pushforward (Lemma on c-transform properties (ii) with
- * h = |.|^2/2; pushforward of Section 2.1).  T = x - grad phic (central
- * differences, one-sided at faces, clamped to the cell-centre box) and
+/* Primitive: map and pushforward (Lemma on c-transform properties (ii);
+ * pushforward of Section 2.1).  T = x - grad phic for h = |.|^2/2, or
+ * component a of T = x_a - sign(g_a)|g_a|^{1/(p_a - 1)} with g = grad phic
+ * for the power costs (central differences, one-sided at faces, clamped to
+ * the cell-centre box) and
  * rho = T#mass by cloud-in-cell deposition (multilinear weights).
  *   phic, mass  device inputs, N elements.
  *   rho         device output density, N elements (overwritten).
  *   T           device output, ndim*N elements, or NULL.
- *   primal      host output or NULL: int |x - T(x)|^2/2 dmass (synchronises). */
+ *   primal      host output or NULL: int c(x, T(x)) dmass (synchronises). */
 bfm_status bfm_pushforward(bfm_plan plan, const void *phic, const void *mass, void *rho, void *T,
                            double *primal, void *workspace, size_t ws_bytes, void *stream);
 
@@ -230,7 +235,8 @@ bfm_status bfm_grad(bfm_plan plan, const void *phi, const void *psi, double scal
 
 /* Primitive: one separable pass of the c-transform along `axis` (the
  * one-dimensional step of Section 4.1): for every grid line along that axis
- *   out_i = min_j (x_i - y_j)^2 / 2 + sign * in_j .
+ *   out_i = min_j h_axis(x_i - y_j) + sign * in_j ,
+ * h_axis(z) = z^2 / 2, or |z|^p / p with p = params.power[axis].
  * sign is +1 or -1 (the first pass of a transform uses -1).  in/out are
  * device fields of N elements; out may equal in.  Exposed for measurement
  * and tests. */
