@@ -253,14 +253,24 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
         // box bounds: reduce across the wave first, one LDS atomic per wave
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                bmin[a] = min(bmin[a], __shfl_xor(bmin[a], o, kWave));
-                bmax[a] = max(bmax[a], __shfl_xor(bmax[a], o, kWave));
-            }
-            if ((threadIdx.x & (kWave - 1)) == 0 && bmax[a] >= 0) {
-                atomicMin(&bb[a], bmin[a]);
-                atomicMax(&bb[D + a], bmax[a]);
+            // rotations inside each 16-lane row (DPP), then the four row
+            // results read out to scalars: no LDS permutes on this path
+            int vmn = bmin[a], vmx = bmax[a];
+            vmn = min(vmn, __builtin_amdgcn_update_dpp(vmn, vmn, 0x121, 0xf, 0xf, false));
+            vmx = max(vmx, __builtin_amdgcn_update_dpp(vmx, vmx, 0x121, 0xf, 0xf, false));
+            vmn = min(vmn, __builtin_amdgcn_update_dpp(vmn, vmn, 0x122, 0xf, 0xf, false));
+            vmx = max(vmx, __builtin_amdgcn_update_dpp(vmx, vmx, 0x122, 0xf, 0xf, false));
+            vmn = min(vmn, __builtin_amdgcn_update_dpp(vmn, vmn, 0x124, 0xf, 0xf, false));
+            vmx = max(vmx, __builtin_amdgcn_update_dpp(vmx, vmx, 0x124, 0xf, 0xf, false));
+            vmn = min(vmn, __builtin_amdgcn_update_dpp(vmn, vmn, 0x128, 0xf, 0xf, false));
+            vmx = max(vmx, __builtin_amdgcn_update_dpp(vmx, vmx, 0x128, 0xf, 0xf, false));
+            const int wmn = min(min(__builtin_amdgcn_readlane(vmn, 0), __builtin_amdgcn_readlane(vmn, 16)),
+                                min(__builtin_amdgcn_readlane(vmn, 32), __builtin_amdgcn_readlane(vmn, 48)));
+            const int wmx = max(max(__builtin_amdgcn_readlane(vmx, 0), __builtin_amdgcn_readlane(vmx, 16)),
+                                max(__builtin_amdgcn_readlane(vmx, 32), __builtin_amdgcn_readlane(vmx, 48)));
+            if ((threadIdx.x & (kWave - 1)) == 0 && wmx >= 0) {
+                atomicMin(&bb[a], wmn);
+                atomicMax(&bb[D + a], wmx);
             }
         }
         __syncthreads();
