@@ -179,6 +179,30 @@ __device__ double slot_reduce_min(const double *partials, long long slot_len, in
     return block_reduce<R_MIN>(v, sh);
 }
 
+// K block sums at once (valid in thread 0), each in the order of
+// slot_reduce_sum: per-thread strided partial, wave sum, waves in order.
+// One pair of barriers for all K instead of one per sum.
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double *sh)
+{
+    constexpr int NW = kRedBlock / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k * NW + w] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double r = sh[k * NW];
+            for (int i = 1; i < NW; ++i) r += sh[k * NW + i];
+            v[k] = r;
+        }
+    __syncthreads();
+}
+
 __device__ double step_rule(double sigma, double increase, double G, const CtrlParams &p)
 {
     if (increase < p.beta1 * sigma * G) return fmax(p.alpha2 * sigma, p.sigma_min);
@@ -190,7 +214,7 @@ __global__ void __launch_bounds__(kRedBlock)
 ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__restrict__ gpart, int mode,
             CtrlParams prm, TraceRec *trace)
 {
-    __shared__ double sh[kRedBlock / kWave];
+    __shared__ double sh[4 * (kRedBlock / kWave)];
     const int nb = prm.nred, ns = prm.nsplat, ng = prm.ngpart;
     const long long sl = prm.slot_len;
     const bool reuse_dot = (mode & CTRL_REUSE_DOT) != 0;
@@ -233,12 +257,18 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
     }
     if (st->done) return;
     if (mode == CTRL_HEAD_PHI || mode == CTRL_HEAD_PSI) {
-        const double a = reuse_dot ? st->q_src : slot_reduce_sum(partials, sl, S_P_TGT, nb, sh);
-        const double b = slot_reduce_sum(partials, sl, S_PC_SRC, ns, sh);
-        const double P = slot_reduce_sum(partials, sl, S_PRIMAL, ns, sh);
-        double gv = 0.0;
-        for (int i = threadIdx.x; i < ng; i += blockDim.x) gv += gpart[i];
-        const double G = block_reduce<R_SUM>(gv, sh);
+        // sum p * tgt (unless reused), sum pc * src, the primal cost, G
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!reuse_dot)
+            for (int i = threadIdx.x; i < nb; i += blockDim.x) acc[0] += partials[S_P_TGT * sl + i];
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            acc[1] += partials[S_PC_SRC * sl + i];
+            acc[2] += partials[S_PRIMAL * sl + i];
+        }
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) acc[3] += gpart[i];
+        block_sums<4>(acc, sh);
+        const double a = reuse_dot ? st->q_src : acc[0];
+        const double b = acc[1], P = acc[2], G = acc[3];
         if (threadIdx.x == 0) {
             st->J_old = prm.vol * (a + b);
             st->P = prm.vol * P;
@@ -284,8 +314,11 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
         return;
     }
     if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
-        const double a = slot_reduce_sum(partials, sl, S_Q_TGT, prm.nqt, sh);
-        const double b = slot_reduce_sum(partials, sl, S_Q_SRC, prm.nqs, sh);
+        double acc[2] = {0.0, 0.0};
+        for (int i = threadIdx.x; i < prm.nqt; i += blockDim.x) acc[0] += partials[S_Q_TGT * sl + i];
+        for (int i = threadIdx.x; i < prm.nqs; i += blockDim.x) acc[1] += partials[S_Q_SRC * sl + i];
+        block_sums<2>(acc, sh);
+        const double a = acc[0], b = acc[1];
         if (threadIdx.x == 0) {
             st->q_src = b;
             st->J_new = prm.vol * (a + b);
