@@ -149,7 +149,7 @@ def test_w2_loss_batched_gradients_equal_single():
         b = cuda(n).requires_grad_(True)
         l1 = bfm.w2_loss(a, b, max_iters=30, tol=0.0)
         (l1 * [1.0, 2.0, -1.0][i]).backward()
-        assert abs(float(l1) - float(vals[i])) <= 1e-10
+        assert abs(float(l1.detach()) - float(vals[i].detach())) <= 1e-10
         for x, y in ((a.grad, mus[i].grad), (b.grad, nus[i].grad)):
             assert float((x - y).abs().max()) <= 1e-8 * float(y.abs().max())
 
