@@ -127,3 +127,16 @@ def test_plan_python_validation():
     with pytest.raises(ValueError):
         bfm.Plan((32, 32), method="newton")
     assert bfm.Plan((32, 32), method="ga").params.method == 1
+
+
+def test_header_is_plain_c():
+    """The boundary header compiles as C99 (no C++ types cross the ABI)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bfm.h")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", "c", hdr],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
