@@ -160,6 +160,9 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
         else __syncthreads();
         if ((t & (2 * r - 1)) == 0 && t + r < tpl) {
             const int hL = GH[t], tL = GT[t], hR = GH[t + r], tR = GT[t + r];
+            // all four ends in one LDS round trip (the branches below would
+            // otherwise make the compiler wait for them one after another)
+            __asm__ volatile("" ::"v"(hL), "v"(tL), "v"(hR), "v"(tR));
             if (hR >= 0) {
                 if (hL < 0) {
                     GH[t] = hR;
