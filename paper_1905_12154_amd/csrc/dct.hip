@@ -295,6 +295,11 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
                  const T *__restrict__ dotw, const int32_t *__restrict__ done)
 {
     if (done != nullptr && *done) return;
+    // Vector loads per thread (the launch guarantees n <= 16 bd): contiguous
+    // lines take n / (4 bd) <= 4 per line, the two-pair strided form
+    // n / (2 bd) <= 8.  Each load loop issues all of them before the first
+    // LDS write, so their latencies overlap.
+    constexpr int kContigIt = 4, kStridedIt = 8;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[8];
     const int n = ax.n, inner = ax.inner;
@@ -315,20 +320,32 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
         if (CONTIG) {
             const long long ba = La * n, bbb = Lb * n;
             const bool vec = (n & 3) == 0 && al16;
-            for (int k4 = lt * 4; k4 < n; k4 += bd * 4) {
-                if (vec) {
-                    typename v4t<T>::type xa = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + k4);
-                    typename v4t<T>::type xb;
-                    if (hasb) xb = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + k4);
-                    else xb.x = xb.y = xb.z = xb.w = T(0);
-                    buf[padc(k4)] = {xa.x, xb.x};
-                    buf[padc(k4 + 1)] = {xa.y, xb.y};
-                    buf[padc(k4 + 2)] = {xa.z, xb.z};
-                    buf[padc(k4 + 3)] = {xa.w, xb.w};
-                } else {
+            if (vec) {
+                // every load of the thread is issued before its first LDS write
+                typename v4t<T>::type xa[kContigIt], xb[kContigIt];
+#pragma unroll
+                for (int q = 0; q < kContigIt; ++q) {
+                    const int k4 = (lt + q * bd) * 4;
+                    if (k4 < n) {
+                        xa[q] = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + k4);
+                        if (hasb) xb[q] = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + k4);
+                        else xb[q].x = xb[q].y = xb[q].z = xb[q].w = T(0);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kContigIt; ++q) {
+                    const int k4 = (lt + q * bd) * 4;
+                    if (k4 < n) {
+                        buf[padc(k4)] = {xa[q].x, xb[q].x};
+                        buf[padc(k4 + 1)] = {xa[q].y, xb[q].y};
+                        buf[padc(k4 + 2)] = {xa[q].z, xb[q].z};
+                        buf[padc(k4 + 3)] = {xa[q].w, xb[q].w};
+                    }
+                }
+            } else {
+                for (int k4 = lt * 4; k4 < n; k4 += bd * 4)
                     for (int e = 0; e < 4; ++e)
                         if (k4 + e < n) buf[padc(k4 + e)] = {hasa ? a[ba + k4 + e] : T(0), hasb ? a[bbb + k4 + e] : T(0)};
-                }
             }
         } else {
             const bool vec = NPAIR == 2 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= ax.nlines && al16;
@@ -336,11 +353,19 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
             cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
             cpx<T> *buf1 = buf0 + NPC;
             if (vec) {
-                for (int k = threadIdx.x; k < n; k += blockDim.x) {
-                    const typename v4t<T>::type x =
-                        *reinterpret_cast<const typename v4t<T>::type *>(a + b0 + (long long)k * inner);
-                    buf0[padc(k)] = {x.x, x.y};
-                    buf1[padc(k)] = {x.z, x.w};
+                typename v4t<T>::type xs[kStridedIt];
+#pragma unroll
+                for (int q = 0; q < kStridedIt; ++q) {
+                    const int k = threadIdx.x + q * blockDim.x;
+                    if (k < n) xs[q] = *reinterpret_cast<const typename v4t<T>::type *>(a + b0 + (long long)k * inner);
+                }
+#pragma unroll
+                for (int q = 0; q < kStridedIt; ++q) {
+                    const int k = threadIdx.x + q * blockDim.x;
+                    if (k < n) {
+                        buf0[padc(k)] = {xs[q].x, xs[q].y};
+                        buf1[padc(k)] = {xs[q].z, xs[q].w};
+                    }
                 }
             } else {
                 for (int k = lt; k < n; k += bd)
@@ -366,36 +391,54 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
         if (CONTIG) {
             const long long ba = La * n, bbb = Lb * n;
             const bool vec = (n & 3) == 0 && al16;
-            for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
-                T xa[4], xb[4];
-                if (vec) {
-                    typename v4t<T>::type va4 = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + j4);
-                    typename v4t<T>::type vb4;
-                    if (hasb) vb4 = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + j4);
-                    else vb4.x = vb4.y = vb4.z = vb4.w = T(0);
-                    if (b != nullptr) {
-                        const typename v4t<T>::type ra = *reinterpret_cast<const typename v4t<T>::type *>(b + ba + j4);
-                        va4.x -= ra.x; va4.y -= ra.y; va4.z -= ra.z; va4.w -= ra.w;
-                        if (hasb) {
-                            const typename v4t<T>::type rb =
-                                *reinterpret_cast<const typename v4t<T>::type *>(b + bbb + j4);
-                            vb4.x -= rb.x; vb4.y -= rb.y; vb4.z -= rb.z; vb4.w -= rb.w;
-                        }
-                        if (zero_b) {
-                            typename v4t<T>::type z;
-                            z.x = z.y = z.z = z.w = T(0);
-                            *reinterpret_cast<typename v4t<T>::type *>(b + ba + j4) = z;
-                            if (hasb) *reinterpret_cast<typename v4t<T>::type *>(b + bbb + j4) = z;
+            if (vec) {
+                // all loads of a chunk are issued before its first LDS write
+                constexpr int QN = sizeof(T) == 4 ? kContigIt : kContigIt / 2;
+#pragma unroll
+                for (int q0 = 0; q0 < kContigIt; q0 += QN) {
+                    typename v4t<T>::type va[QN], vb[QN], ra[QN], rb[QN];
+#pragma unroll
+                    for (int q = 0; q < QN; ++q) {
+                        const int j4 = (lt + (q0 + q) * bd) * 4;
+                        if (j4 < n) {
+                            va[q] = *reinterpret_cast<const typename v4t<T>::type *>(a + ba + j4);
+                            if (hasb) vb[q] = *reinterpret_cast<const typename v4t<T>::type *>(a + bbb + j4);
+                            if (b != nullptr) {
+                                ra[q] = *reinterpret_cast<const typename v4t<T>::type *>(b + ba + j4);
+                                if (hasb) rb[q] = *reinterpret_cast<const typename v4t<T>::type *>(b + bbb + j4);
+                            }
                         }
                     }
-                    xa[0] = va4.x; xa[1] = va4.y; xa[2] = va4.z; xa[3] = va4.w;
-                    xb[0] = vb4.x; xb[1] = vb4.y; xb[2] = vb4.z; xb[3] = vb4.w;
-                    // x_{j4}, x_{j4+2} are even samples, x_{j4+1}, x_{j4+3} odd
-                    buf[padc(j4 / 2)] = {xa[0], xb[0]};
-                    buf[padc(j4 / 2 + 1)] = {xa[2], xb[2]};
-                    buf[padc(n - 1 - j4 / 2)] = {xa[1], xb[1]};
-                    buf[padc(n - 2 - j4 / 2)] = {xa[3], xb[3]};
-                } else {
+#pragma unroll
+                    for (int q = 0; q < QN; ++q) {
+                        const int j4 = (lt + (q0 + q) * bd) * 4;
+                        if (j4 >= n) continue;
+                        T xa[4] = {va[q].x, va[q].y, va[q].z, va[q].w};
+                        T xb[4] = {T(0), T(0), T(0), T(0)};
+                        if (hasb) {
+                            xb[0] = vb[q].x; xb[1] = vb[q].y; xb[2] = vb[q].z; xb[3] = vb[q].w;
+                        }
+                        if (b != nullptr) {
+                            xa[0] -= ra[q].x; xa[1] -= ra[q].y; xa[2] -= ra[q].z; xa[3] -= ra[q].w;
+                            if (hasb) {
+                                xb[0] -= rb[q].x; xb[1] -= rb[q].y; xb[2] -= rb[q].z; xb[3] -= rb[q].w;
+                            }
+                            if (zero_b) {
+                                typename v4t<T>::type z;
+                                z.x = z.y = z.z = z.w = T(0);
+                                *reinterpret_cast<typename v4t<T>::type *>(b + ba + j4) = z;
+                                if (hasb) *reinterpret_cast<typename v4t<T>::type *>(b + bbb + j4) = z;
+                            }
+                        }
+                        // x_{j4}, x_{j4+2} are even samples, x_{j4+1}, x_{j4+3} odd
+                        buf[padc(j4 / 2)] = {xa[0], xb[0]};
+                        buf[padc(j4 / 2 + 1)] = {xa[2], xb[2]};
+                        buf[padc(n - 1 - j4 / 2)] = {xa[1], xb[1]};
+                        buf[padc(n - 2 - j4 / 2)] = {xa[3], xb[3]};
+                    }
+                }
+            } else {
+                for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
                     #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (j4 + e >= n) break;
@@ -420,11 +463,21 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
             cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
             cpx<T> *buf1 = buf0 + NPC;
             if (vec) {
-                for (int j = threadIdx.x; j < n; j += blockDim.x) {
-                    const typename v4t<T>::type x = *reinterpret_cast<const typename v4t<T>::type *>(
-                        a + b0 + (long long)makhoul_src(j, n) * inner);
-                    buf0[padc(j)] = {x.x, x.y};
-                    buf1[padc(j)] = {x.z, x.w};
+                typename v4t<T>::type xs[kStridedIt];
+#pragma unroll
+                for (int q = 0; q < kStridedIt; ++q) {
+                    const int j = threadIdx.x + q * blockDim.x;
+                    if (j < n)
+                        xs[q] = *reinterpret_cast<const typename v4t<T>::type *>(
+                            a + b0 + (long long)makhoul_src(j, n) * inner);
+                }
+#pragma unroll
+                for (int q = 0; q < kStridedIt; ++q) {
+                    const int j = threadIdx.x + q * blockDim.x;
+                    if (j < n) {
+                        buf0[padc(j)] = {xs[q].x, xs[q].y};
+                        buf1[padc(j)] = {xs[q].z, xs[q].w};
+                    }
                 }
             } else {
                 for (int j = lt; j < n; j += bd) {
@@ -551,42 +604,76 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
         if (CONTIG) {
             const long long ba = La * n, bbb = Lb * n;
             const bool vec = (n & 3) == 0 && al16;
-            for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
-                T xa[4], xb[4];
-                #pragma unroll
+            if (vec) {
+                // the reads of p and of the weights are issued before the outputs are formed
+                constexpr int QN = sizeof(T) == 4 ? kContigIt : kContigIt / 2;
+#pragma unroll
+                for (int q0 = 0; q0 < kContigIt; q0 += QN) {
+                    typename v4t<T>::type pa[QN], pb[QN], wa[QN], wb[QN];
+#pragma unroll
+                    for (int q = 0; q < QN; ++q) {
+                        const int j4 = (lt + (q0 + q) * bd) * 4;
+                        if (j4 < n) {
+                            if (base != nullptr) {
+                                pa[q] = *reinterpret_cast<const typename v4t<T>::type *>(base + ba + j4);
+                                if (hasb) pb[q] = *reinterpret_cast<const typename v4t<T>::type *>(base + bbb + j4);
+                            }
+                            if (dotw != nullptr) {
+                                wa[q] = *reinterpret_cast<const typename v4t<T>::type *>(dotw + ba + j4);
+                                if (hasb) wb[q] = *reinterpret_cast<const typename v4t<T>::type *>(dotw + bbb + j4);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < QN; ++q) {
+                        const int j4 = (lt + (q0 + q) * bd) * 4;
+                        if (j4 >= n) continue;
+                    T xa[4], xb[4];
+                    #pragma unroll
                     for (int e = 0; e < 4; ++e) {
+                        xa[e] = xb[e] = T(0);
                         if (j4 + e >= n) break;
-                    const int jj = j4 + e;
-                    const int pos = (jj & 1) ? n - 1 - (jj >> 1) : (jj >> 1);
-                    const cpx<T> z = buf[padc(pos)];
-                    xa[e] = z.x * inv_n;
-                    xb[e] = -z.y * inv_n;
+                        const int jj = j4 + e;
+                        const int pos = (jj & 1) ? n - 1 - (jj >> 1) : (jj >> 1);
+                        const cpx<T> z = buf[padc(pos)];
+                        xa[e] = z.x * inv_n;
+                        xb[e] = -z.y * inv_n;
+                    }
+                        typename v4t<T>::type oa, ob;
+                        oa.x = xa[0]; oa.y = xa[1]; oa.z = xa[2]; oa.w = xa[3];
+                        ob.x = xb[0]; ob.y = xb[1]; ob.z = xb[2]; ob.w = xb[3];
+                        if (base != nullptr) {
+                            oa.x = pa[q].x + sc * oa.x; oa.y = pa[q].y + sc * oa.y;
+                            oa.z = pa[q].z + sc * oa.z; oa.w = pa[q].w + sc * oa.w;
+                            if (hasb) {
+                                ob.x = pb[q].x + sc * ob.x; ob.y = pb[q].y + sc * ob.y;
+                                ob.z = pb[q].z + sc * ob.z; ob.w = pb[q].w + sc * ob.w;
+                            }
+                        }
+                        if (hasa) *reinterpret_cast<typename v4t<T>::type *>(out + ba + j4) = oa;
+                        if (hasb) *reinterpret_cast<typename v4t<T>::type *>(out + bbb + j4) = ob;
+                        if (dotw != nullptr) {   // sum out * dotw of the written values
+                            gacc += (double)oa.x * wa[q].x + (double)oa.y * wa[q].y + (double)oa.z * wa[q].z +
+                                    (double)oa.w * wa[q].w;
+                            if (hasb)
+                                gacc += (double)ob.x * wb[q].x + (double)ob.y * wb[q].y + (double)ob.z * wb[q].z +
+                                        (double)ob.w * wb[q].w;
+                        }
+                    }
                 }
-                if (vec) {
-                    typename v4t<T>::type oa, ob;
-                    oa.x = xa[0]; oa.y = xa[1]; oa.z = xa[2]; oa.w = xa[3];
-                    ob.x = xb[0]; ob.y = xb[1]; ob.z = xb[2]; ob.w = xb[3];
-                    if (base != nullptr) {
-                        const typename v4t<T>::type pa = *reinterpret_cast<const typename v4t<T>::type *>(base + ba + j4);
-                        oa.x = pa.x + sc * oa.x; oa.y = pa.y + sc * oa.y; oa.z = pa.z + sc * oa.z; oa.w = pa.w + sc * oa.w;
-                        if (hasb) {
-                            const typename v4t<T>::type pb =
-                                *reinterpret_cast<const typename v4t<T>::type *>(base + bbb + j4);
-                            ob.x = pb.x + sc * ob.x; ob.y = pb.y + sc * ob.y; ob.z = pb.z + sc * ob.z; ob.w = pb.w + sc * ob.w;
-                        }
+            } else {
+                for (int j4 = lt * 4; j4 < n; j4 += bd * 4) {
+                    T xa[4], xb[4];
+                    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        xa[e] = xb[e] = T(0);
+                        if (j4 + e >= n) break;
+                        const int jj = j4 + e;
+                        const int pos = (jj & 1) ? n - 1 - (jj >> 1) : (jj >> 1);
+                        const cpx<T> z = buf[padc(pos)];
+                        xa[e] = z.x * inv_n;
+                        xb[e] = -z.y * inv_n;
                     }
-                    if (hasa) *reinterpret_cast<typename v4t<T>::type *>(out + ba + j4) = oa;
-                    if (hasb) *reinterpret_cast<typename v4t<T>::type *>(out + bbb + j4) = ob;
-                    if (dotw != nullptr) {   // sum out * dotw of the written values
-                        const typename v4t<T>::type wa = *reinterpret_cast<const typename v4t<T>::type *>(dotw + ba + j4);
-                        gacc += (double)oa.x * wa.x + (double)oa.y * wa.y + (double)oa.z * wa.z + (double)oa.w * wa.w;
-                        if (hasb) {
-                            const typename v4t<T>::type wb =
-                                *reinterpret_cast<const typename v4t<T>::type *>(dotw + bbb + j4);
-                            gacc += (double)ob.x * wb.x + (double)ob.y * wb.y + (double)ob.z * wb.z + (double)ob.w * wb.w;
-                        }
-                    }
-                } else {
                     #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (j4 + e >= n) break;
