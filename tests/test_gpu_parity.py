@@ -198,7 +198,10 @@ def test_ctransform_in_place_and_linear_closed_form():
     assert np.max(np.abs(host(out) - ref)) <= 1e-14
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (96, 384), (6, 4), (24, 32, 18), (4096, 16)])
+# (9, 12), (27, 16), (9, 27, 8): an odd number of contiguous lines, so the last
+# pair of lines has no second line
+@pytest.mark.parametrize("shape", [(64, 64), (96, 384), (6, 4), (24, 32, 18), (4096, 16), (9, 12), (27, 16),
+                                   (9, 27, 8)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_poisson_matches_oracle(shape, dtype):
     f = np.random.default_rng(3).normal(size=shape)
@@ -302,7 +305,7 @@ def test_square_to_four_exact_dual_with_gap_floor():
     assert abs(r.gap - o.gap) <= 1e-9
 
 
-@pytest.mark.parametrize("shape", [(96, 384), (48, 64)])
+@pytest.mark.parametrize("shape", [(96, 384), (48, 64), (27, 48)])
 def test_solve_parity_rectangular(shape):
     rng = np.random.default_rng(9)
     mu = wl.random_gaussian_mixture(shape, 3, rng)
