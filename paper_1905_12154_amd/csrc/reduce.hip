@@ -160,11 +160,27 @@ hipError_t launch_shift_scale(T *out_a, const T *in_a, const double *shift_a, do
     return hipGetLastError();
 }
 
+// acc + x[t] + x[t + B] + x[t + 2B] + ... (t = threadIdx.x, B = blockDim.x,
+// indices < n), added in that order; eight terms are loaded before they are
+// added, so their load latencies overlap.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ x, int n, double acc)
+{
+    const int st = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * st < n; i += 8 * st) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = x[i + k * st];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; i < n; i += st) acc += x[i];
+    return acc;
+}
+
 __device__ double slot_reduce_sum(const double *partials, long long slot_len, int slot, int nb, double *sh)
 {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partials[slot * slot_len + i];
-    return block_reduce<R_SUM>(v, sh);
+    return block_reduce<R_SUM>(strided_sum(partials + slot * slot_len, nb, 0.0), sh);
 }
 __device__ double slot_reduce_max(const double *partials, long long slot_len, int slot, int nb, double *sh)
 {
@@ -258,14 +274,11 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
     if (st->done) return;
     if (mode == CTRL_HEAD_PHI || mode == CTRL_HEAD_PSI) {
         // sum p * tgt (unless reused), sum pc * src, the primal cost, G
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (!reuse_dot)
-            for (int i = threadIdx.x; i < nb; i += blockDim.x) acc[0] += partials[S_P_TGT * sl + i];
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-            acc[1] += partials[S_PC_SRC * sl + i];
-            acc[2] += partials[S_PRIMAL * sl + i];
-        }
-        for (int i = threadIdx.x; i < ng; i += blockDim.x) acc[3] += gpart[i];
+        double acc[4];
+        acc[0] = reuse_dot ? 0.0 : strided_sum(partials + S_P_TGT * sl, nb, 0.0);
+        acc[1] = strided_sum(partials + S_PC_SRC * sl, ns, 0.0);
+        acc[2] = strided_sum(partials + S_PRIMAL * sl, ns, 0.0);
+        acc[3] = strided_sum(gpart, ng, 0.0);
         block_sums<4>(acc, sh);
         const double a = reuse_dot ? st->q_src : acc[0];
         const double b = acc[1], P = acc[2], G = acc[3];
@@ -314,9 +327,9 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
         return;
     }
     if (mode == CTRL_STEP_PHI || mode == CTRL_STEP_PSI) {
-        double acc[2] = {0.0, 0.0};
-        for (int i = threadIdx.x; i < prm.nqt; i += blockDim.x) acc[0] += partials[S_Q_TGT * sl + i];
-        for (int i = threadIdx.x; i < prm.nqs; i += blockDim.x) acc[1] += partials[S_Q_SRC * sl + i];
+        double acc[2];
+        acc[0] = strided_sum(partials + S_Q_TGT * sl, prm.nqt, 0.0);
+        acc[1] = strided_sum(partials + S_Q_SRC * sl, prm.nqs, 0.0);
         block_sums<2>(acc, sh);
         const double a = acc[0], b = acc[1];
         if (threadIdx.x == 0) {
