@@ -608,27 +608,9 @@ size_t ct_smem_bytes(int n, int tpl, int lpb) { return ct_smem_for(n, tpl, lpb, 
 // Workgroups resident at once for a kernel (the persistent grid size).
 static long long resident_blocks(const void *fn, int threads, size_t smem)
 {
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-            ncu = 256;
-    }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, smem) != hipSuccess || occ < 1) occ = 1;
-    return (long long)occ * ncu;
-}
-
-template <typename KernelT>
-static hipError_t allow_smem(KernelT fn, size_t smem, bool &done_flag)
-{
-    if (smem > 64 * 1024 && !done_flag) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-        if (e != hipSuccess) return e;
-        done_flag = true;
-    }
-    return hipSuccess;
+    return (long long)occ * device_cu_count();
 }
 
 template <typename T, int C, int LPB, bool STRIDED, bool BLK>
@@ -636,11 +618,11 @@ static hipError_t launch_pf(const T *in, T *out, int n, int inner, long long nli
                             const int32_t *done, hipStream_t stream, const T *dotw = nullptr,
                             double *dotpart = nullptr, int *ndot = nullptr)
 {
-    static bool attr = false;
+    static size_t lds_limit[kMaxDevices] = {};
     const size_t smem = ct_smem_bytes<T>(n, tpl, LPB);
     const long long groups = (nlines + LPB - 1) / LPB;
     auto fn = ct_lines_pf_kernel<T, C, LPB, STRIDED, BLK>;
-    hipError_t e = allow_smem(fn, smem, attr);
+    hipError_t e = raise_dyn_lds((const void *)fn, smem, lds_limit);
     if (e != hipSuccess) return e;
     long long blocks = resident_blocks((const void *)fn, threads, smem);
     if (blocks > groups) blocks = groups;
@@ -679,8 +661,8 @@ static hipError_t launch_ct_impl(const T *in, T *out, int n, int inner, long lon
         return hipErrorInvalidValue;
     }
     if (blk) return hipErrorInvalidValue;
-    static bool attr = false;
-    hipError_t e = allow_smem(ct_lines_kernel<T, C, LPB>, smem, attr);
+    static size_t lds_limit[kMaxDevices] = {};
+    hipError_t e = raise_dyn_lds((const void *)ct_lines_kernel<T, C, LPB>, smem, lds_limit);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((ct_lines_kernel<T, C, LPB>), dim3((unsigned)groups), dim3(threads), smem, stream, in,
                        out, n, inner, nlines, tpl, sgn, h, done);

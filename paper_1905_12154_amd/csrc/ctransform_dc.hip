@@ -208,21 +208,10 @@ hipError_t launch_ct_dc(const T *in, T *out, int n, int inner, long long nlines,
 {
     if (n < 2 || n > 4096 || nlines <= 0 || !(p > 1.0)) return hipErrorInvalidValue;
     const size_t smem = dc_smem_bytes<T>(n);
-    static bool raised[2] = {false, false};
-    bool &r = raised[sizeof(T) == 8];
-    if (smem > 64 * 1024 && !r) {
-        hipError_t e = hipFuncSetAttribute((const void *)ct_dc_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)smem);
-        if (e != hipSuccess) return e;
-        r = true;
-    }
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-            ncu = 256;
-    }
+    static size_t lds_limit[kMaxDevices] = {};
+    hipError_t e = raise_dyn_lds((const void *)ct_dc_kernel<T>, smem, lds_limit);
+    if (e != hipSuccess) return e;
+    const int ncu = device_cu_count();
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)ct_dc_kernel<T>, kDcBlock, smem) !=
             hipSuccess ||

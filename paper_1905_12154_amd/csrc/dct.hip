@@ -745,15 +745,9 @@ static hipError_t launch_dct_impl(const T *a, T *b, T *out, const T *base, const
     if (bd * NPAIR > 512) return hipErrorInvalidValue;
     const size_t smem = (size_t)NPAIR * padc_len(ax.n) * sizeof(cpx<T>);
     const long long blocks = (ax.nlines + 2 * NPAIR - 1) / (2 * NPAIR);
-    if (smem > 64 * 1024) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
-    }
+    static size_t lds_limit[kMaxDevices] = {};
+    hipError_t e = raise_dyn_lds((const void *)dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>, smem, lds_limit);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((dct_lines_kernel<T, 16, NPAIR, MODE, CONTIG>), dim3((unsigned)blocks), dim3(bd * NPAIR),
                        smem, stream, a, b, out, base, scale, ax, zero_b, (const cpx<T> *)tw, (const cpx<T> *)qw,
                        lam0, lamA, lamB, gpart, dotw, done);

@@ -5,14 +5,48 @@
 
 namespace bfm {
 
-// Per-axis spectral plan: FFT stage counts (n = 4^n4 2^n2 3^n3 packed as
-// n4 | n2 << 8 | n3 << 16) and the stride of the axis.
+// Per-axis spectral plan: FFT stage counts (n = 16^a 8^b 4^c 2^d 3^e packed
+// as a | b << 6 | c << 12 | d << 18 | e << 24) and the stride of the axis.
 struct AxisPlan {
     int n;
     int inner;
     uint32_t radices;
     int nstages;
 };
+
+// Launch facts kept per device (ids below kMaxDevices; for others they are
+// looked up or set again at every call).
+constexpr int kMaxDevices = 64;
+
+// Compute units of the current device.
+inline int device_cu_count()
+{
+    static int ncu[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    const bool known = dev >= 0 && dev < kMaxDevices;
+    if (known && ncu[dev] > 0) return ncu[dev];
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    if (known) ncu[dev] = n;
+    return n;
+}
+
+// Raises fn's dynamic LDS limit on the current device to `bytes` when that
+// exceeds the 64 KB default and what was set before; `limit` (one array per
+// kernel) records per device the largest value set so far.
+inline hipError_t raise_dyn_lds(const void *fn, size_t bytes, size_t (&limit)[kMaxDevices])
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const bool known = dev >= 0 && dev < kMaxDevices;
+    if (known && limit[dev] >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess && known) limit[dev] = bytes;
+    return e;
+}
 
 // c-transform (ctransform.hip).  CtCfg overrides the launch shape of one
 // axis (0 = built-in choice): C points per lane, lines per workgroup on a
