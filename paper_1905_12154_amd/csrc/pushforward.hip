@@ -19,7 +19,7 @@
 // displacement interpolant S_t(x) = t T(x) + (1 - t) x (Section 4.3,
 // optimal transport of images), t = tmix.
 //
-// Deposition: source cells are processed by compact tiles (32 x 32 in 2D,
+// Deposition: source cells are processed by compact tiles (16 x 32 in 2D,
 // 8 x 8 x 8 in 3D).  Where the map compresses mass, many sources of a tile
 // land on few target cells, and global atomics on the same addresses
 // serialise; so the workgroup first accumulates its deposits in an LDS box
@@ -35,13 +35,15 @@
 namespace bfm {
 
 // LDS box: 32 KB in 2D, 16 KB in 3D.  A 2D tile's targets overflow the box
-// only where the map expands by more than about 2.8 per axis; the
+// only where the map expands by more than about 4 per axis; the
 // workgroups per CU are set by registers, not by this LDS.  In 3D a larger
 // box was slower.
 template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 32768) / (int)sizeof(T); }
 
 template <int D> struct Tile;
-template <> struct Tile<2> { static constexpr int s[2] = {32, 32}; static constexpr int cells = 1024; };
+// 2D: 16 x 32 tiles (two cells per lane) spread the tiles with mass of a
+// compactly supported density over more workgroups than 32 x 32 did.
+template <> struct Tile<2> { static constexpr int s[2] = {16, 32}; static constexpr int cells = 512; };
 template <> struct Tile<3> { static constexpr int s[3] = {8, 8, 8}; static constexpr int cells = 512; };
 
 // One deposit per lane into the LDS box (key = box cell, or < 0 for none;
