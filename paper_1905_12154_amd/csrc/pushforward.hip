@@ -35,9 +35,10 @@
 namespace bfm {
 
 // LDS box: 32 KB in 2D, 16 KB in 3D.  A 2D tile's targets overflow the box
-// only where the map expands by more than about 4 per axis; the
-// workgroups per CU are set by registers, not by this LDS.  In 3D a larger
-// box was slower.
+// only where the map expands by more than about 4 per axis.  In 2D the box
+// sets four workgroups per CU (registers would allow six), but smaller
+// boxes overflow to global atomics more often and were slower; in 3D a
+// larger box was slower.
 template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 32768) / (int)sizeof(T); }
 
 template <int D> struct Tile;
