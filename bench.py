@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--ga-cap", type=int, default=3000, help="iteration cap of the gradient-ascent runs")
     ap.add_argument("--no-pcost", action="store_true", help="skip the power-cost leg (crossing discs, 1024^2)")
     ap.add_argument("--pcost-iters", type=int, default=60)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the float32-against-float64 comparison on the headline workload")
+    ap.add_argument("--precision-iters", type=int, default=200, help="iteration cap of the precision leg")
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
@@ -329,6 +332,47 @@ def pcost_leg(iters, n=1024):
             "runs": rows, "ctransform_ms": ct_ms}
 
 
+def precision_leg(n, iters, tol=1e-4):
+    """The float32 production path against the float64 path of the same
+    kernels on the headline workload (c3, n^2): each precision solves from
+    phi = 0 to a dual gap below `tol` (at most `iters` iterations), then the
+    relative differences of the dual and of W2^2, the map difference in grid
+    cells over the support of mu (where the map transports mass) and the
+    largest difference of the potential phi.  Agreement of the float64 path
+    with the float64 CPU oracle is what the parity tests check, at the sizes
+    the oracle finishes."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c3(n)
+    res = {}
+    for dt in (torch.float64, torch.float32):
+        mu = torch.tensor(mu_h, dtype=dt, device=dev)
+        nu = torch.tensor(nu_h, dtype=dt, device=dev)
+        plan = bfm.Plan((n, n), dt, max_iters=iters, tol=tol, check_every=4)
+        r = plan.solve(mu, nu)
+        res[dt] = r
+        sup = mu > 0
+    r64, r32 = res[torch.float64], res[torch.float32]
+    # map difference per source cell in grid cells (largest over the axes);
+    # where the transport splits mass the map jumps, and there rounding of
+    # phi decides which side a finite difference sees, so the distribution
+    # is reported beside the maximum
+    d = torch.stack([(r32.T[a].double() - r64.T[a]).abs() for a in range(2)]).amax(0)[sup] * n
+    q = torch.quantile(d.float(), torch.tensor([0.5, 0.999], device=dev)).tolist()
+    return {"workload": "c3: %d^2, 8-disk indicators; float32 path against the float64 path" % n,
+            "tol": tol, "iters_f64": r64.iters, "iters_f32": r32.iters, "gap_f64": r64.gap, "gap_f32": r32.gap,
+            "dual_f64": r64.dual, "dual_f32": r32.dual,
+            "rel_diff_dual": abs(r32.dual - r64.dual) / abs(r64.dual),
+            "rel_diff_w2sq": abs(r32.w2sq - r64.w2sq) / abs(r64.w2sq),
+            "map_diff_cells_on_support": {"cells": int(d.numel()), "mean": float(d.mean()), "median": q[0],
+                                          "p99_9": q[1], "max": float(d.max()),
+                                          "frac_above_0_01": float((d > 0.01).double().mean()),
+                                          "frac_above_1": float((d > 1.0).double().mean())},
+            "max_phi_diff": float((r32.phi.double() - r64.phi).abs().max()),
+            "phi_scale": float(r64.phi.abs().max())}
+
+
 def cpu_baseline(n):
     """The float64 oracle, timed on a bounded sample of one iteration at the
     same grid: 64 lines of each c-transform pass (scaled to all lines), one
@@ -486,6 +530,8 @@ def main():
         out["bfm_vs_ga"] = ga_leg(40, args.ga_cap)
     if not args.no_pcost:
         out["pcost_crossing_discs"] = pcost_leg(args.pcost_iters)
+    if not args.no_precision:
+        out["precision_c3"] = precision_leg(n, args.precision_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(out))
