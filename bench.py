@@ -345,12 +345,17 @@ def precision_leg(n, iters, tol=1e-4):
     from paper_1905_12154_amd import bfm, workloads as wl
     dev = torch.device("cuda:0")
     mu_h, nu_h = wl.config_c3(n)
-    res = {}
+    res, secs = {}, {}
     for dt in (torch.float64, torch.float32):
         mu = torch.tensor(mu_h, dtype=dt, device=dev)
         nu = torch.tensor(nu_h, dtype=dt, device=dev)
         plan = bfm.Plan((n, n), dt, max_iters=iters, tol=tol, check_every=4)
+        plan.solve(mu, nu, return_map=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         r = plan.solve(mu, nu)
+        torch.cuda.synchronize()
+        secs[dt] = time.perf_counter() - t0
         res[dt] = r
         sup = mu > 0
     r64, r32 = res[torch.float64], res[torch.float32]
@@ -362,6 +367,7 @@ def precision_leg(n, iters, tol=1e-4):
     q = torch.quantile(d.float(), torch.tensor([0.5, 0.999], device=dev)).tolist()
     return {"workload": "c3: %d^2, 8-disk indicators; float32 path against the float64 path" % n,
             "tol": tol, "iters_f64": r64.iters, "iters_f32": r32.iters, "gap_f64": r64.gap, "gap_f32": r32.gap,
+            "seconds_f64": secs[torch.float64], "seconds_f32": secs[torch.float32],
             "dual_f64": r64.dual, "dual_f32": r32.dual,
             "rel_diff_dual": abs(r32.dual - r64.dual) / abs(r64.dual),
             "rel_diff_w2sq": abs(r32.w2sq - r64.w2sq) / abs(r64.w2sq),
