@@ -26,6 +26,10 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-pts×iters/s & time to dual gap<1e-4 at 4096²; batched+grad vs plain"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20     # calibration copy: reads and writes this many bytes
+# algorithmic bytes of one whole iteration per grid point, float32: every
+# separable sweep reads its input and writes its output once, with the
+# fusions of the hot path (19 words per half-step in 2D, 27 in 3D)
+ITER_BYTES_PER_POINT = {2: 152, 3: 216}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ct_rows_blocked_sum_c3_4096_f32_traffic.json")
 # sources that decide the c-transform kernel's code: counters taken on
 # another version of them no longer describe the kernel
@@ -70,8 +74,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 64-pair leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3D 384^3 leg")
-    ap.add_argument("--c5-iters", type=int, default=60)
-    ap.add_argument("--c5-tol", type=float, default=1e-4)
+    ap.add_argument("--c5-iters", type=int, default=400)
+    ap.add_argument("--c5-tol", type=float, default=1e-5)
     ap.add_argument("--c4-iters", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-interp", action="store_true", help="skip the 1024^2 displacement-interpolation leg")
@@ -87,9 +91,14 @@ def parse():
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
-    ap.add_argument("--pmc-leg", action="store_true",
-                    help="only the dominant kernel's timing leg plus a %d MiB copy for counter calibration "
-                         "(the program run under rocprofv3 --pmc)" % (COPY_BYTES >> 20))
+    ap.add_argument("--pmc-leg", nargs="?", const="ct", default=None, choices=["ct", "splat3d"],
+                    help="the program run under rocprofv3 --pmc: 'ct' (default) the dominant kernel's timing "
+                         "leg, 'splat3d' three iterations of the 384^3 workload; each followed by a %d MiB "
+                         "copy for counter calibration" % (COPY_BYTES >> 20))
+    ap.add_argument("--oracle-c4-iters", type=int, default=1,
+                    help="iterations of the 384^3 oracle run of the oracle legs (0 skips it)")
+    ap.add_argument("--no-oracle-legs", action="store_true",
+                    help="skip the oracle runs at c1, c2, c4 and on c5 pairs (timing and float32 error)")
     return ap.parse_args()
 
 
@@ -190,6 +199,7 @@ def batched_leg(iters, tol):
             "batched": {"seconds": tb, "pts_iters_per_s": work_b / tb, "converged": sum(r.converged for r in rb),
                         "iters_total": sum(r.iters for r in rb)},
             "batched_plus_grad": {"seconds": tg, "pts_iters_per_s": work_b / tg},
+            "batched_iteration_frac": ITER_BYTES_PER_POINT[2] * work_b / tb / 1e9 / HBM_PEAK_GBS,
             "max_abs_dual_diff_batched_vs_plain": max(abs(a.dual - b.dual) for a, b in zip(rp, rb)),
             "speedup_batched_vs_plain": tp / tb}
 
@@ -213,9 +223,14 @@ def c4_leg(iters, autotune):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     N = mu.numel()
+    ms = dt / max(r.iters, 1) * 1e3
+    gbs = ITER_BYTES_PER_POINT[3] * N / (ms * 1e-3) / 1e9
     return {"workload": "c4: 3D 384^3, 6-Gaussian mixtures, float32", "iters": r.iters, "seconds": dt,
-            "ms_per_iter": dt / max(r.iters, 1) * 1e3, "pts_iters_per_s": N * r.iters / dt, "gap": r.gap,
-            "dual": r.dual, "tuning": plan.tuning()}
+            "ms_per_iter": ms, "pts_iters_per_s": N * r.iters / dt, "gap": r.gap,
+            "dual": r.dual, "tuning": plan.tuning(),
+            "roofline": {"bound": "hbm", "model_bytes_per_point_iter": ITER_BYTES_PER_POINT[3],
+                         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "iteration_frac": gbs / HBM_PEAK_GBS}}
 
 
 def interp_leg(iters, tol, nframes):
@@ -448,6 +463,103 @@ def pmc_leg(n, args):
                       "copy_bytes": COPY_BYTES, "source_sha256": kernel_source_hash()}), flush=True)
 
 
+def pmc_splat3d_leg(iters=3):
+    """What the 3D deposition counter runs profile: `iters` iterations of the
+    384^3 float32 workload from phi = 0 (2 depositions per iteration plus the
+    final head's), then one device copy of COPY_BYTES (the calibration
+    kernel)."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c4()
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    del mu_h, nu_h
+    plan = bfm.Plan(mu.shape, torch.float32, max_iters=iters, check_every=iters)
+    r = plan.solve(mu, nu, return_map=False)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_leg": "splat3d", "iters": r.iters, "dual": r.dual, "copy_bytes": COPY_BYTES}),
+          flush=True)
+
+
+def _map_cells(Tg, To, shape, support):
+    """Largest map difference over the axes, in grid cells of each axis, at
+    the cells of `support`: mean, median, 99.9th percentile, maximum."""
+    import numpy as np
+    d = np.max(np.stack([np.abs(Tg[a] - To[a]) * shape[a] for a in range(len(shape))]), axis=0)[support]
+    if d.size == 0:
+        return None
+    q = np.quantile(d, [0.5, 0.999])
+    return {"cells": int(d.size), "mean": float(d.mean()), "median": float(q[0]), "p99_9": float(q[1]),
+            "max": float(d.max())}
+
+
+def _f32_vs_oracle(mu_h, nu_h, max_iters, tol):
+    """The float32 production path and the float64 CPU oracle on the same
+    input (the oracle takes the float32-rounded densities in float64, so both
+    solve the same problem): the oracle's wall time and cores, and the
+    float32 errors of W2^2 and of the map (grid cells, over supp mu)."""
+    import numpy as np
+    import torch
+    from oracle import bfm as ob
+    from oracle import _native
+    from paper_1905_12154_amd import bfm
+    dev = torch.device("cuda:0")
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    plan = bfm.Plan(mu.shape, torch.float32, max_iters=max_iters, tol=tol, check_every=4)
+    r = plan.solve(mu, nu)
+    Tg = r.T.double().cpu().numpy()
+    gpu = {"iters": r.iters, "converged": bool(r.converged), "w2sq": r.w2sq, "gap": r.gap}
+    del mu, nu
+    m64 = mu_h.astype(np.float32).astype(np.float64)
+    n64 = nu_h.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    o = ob.solve(m64, n64, ob.Params(max_iters=max_iters, tol=tol))
+    secs = time.perf_counter() - t0
+    N = m64.size
+    return {"oracle": {"iters": o.iters, "converged": bool(o.converged), "w2sq": o.w2sq, "gap": o.gap,
+                       "seconds": secs, "pts_iters_per_s": N * max(o.iters, 1) / secs,
+                       "cores": int(_native.lib().oracle_num_threads())},
+            "gpu_f32": gpu,
+            "rel_err_w2sq": abs(r.w2sq - o.w2sq) / abs(o.w2sq),
+            "map_err_cells_on_supp_mu": _map_cells(Tg, np.stack(o.T), m64.shape, m64 > 0)}
+
+
+def oracle_legs(args):
+    """The float64 CPU oracle timed on the configurations it finishes (c1 in
+    full, c2 to its gap, c4 for a few iterations, c5 pairs to their gap), and
+    the float32 GPU path's error against it on each."""
+    from paper_1905_12154_amd import workloads as wl
+    out = {}
+    mu, nu = wl.config_c1()
+    out["c1"] = dict(workload="c1: 64^2, 3-Gaussian mixtures, 60 iterations", **_f32_vs_oracle(mu, nu, 60, 0.0))
+    mu, nu = wl.config_c2()
+    out["c2"] = dict(workload="c2: 1024^2, 5 ellipses to a 4-Gaussian mixture, to gap 1e-5 (cap 2000)",
+                     **_f32_vs_oracle(mu, nu, 2000, 1e-5))
+    del mu, nu
+    if args.oracle_c4_iters > 0:
+        mu, nu = wl.config_c4()
+        out["c4"] = dict(workload="c4: 384^3, 6-Gaussian mixtures, %d iterations" % args.oracle_c4_iters,
+                         **_f32_vs_oracle(mu, nu, args.oracle_c4_iters, 0.0))
+        del mu, nu
+    sides = wl.c5_sides()
+    rows = []
+    for pair in range(64):
+        if len(rows) == 4:
+            break
+        if sides[pair] > 256:
+            continue
+        mu, nu = wl.config_c5_pair(pair, sides[pair])
+        rows.append(dict(pair=pair, side=sides[pair], **_f32_vs_oracle(mu, nu, 300, 1e-5)))
+    out["c5_pairs"] = {"workload": "c5: the first four pairs of side <= 256, to gap 1e-5 (cap 300)", "pairs": rows}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -460,8 +572,11 @@ def main():
 
     dev = torch.device("cuda:0")
     n = args.n
-    if args.pmc_leg:
+    if args.pmc_leg == "ct":
         pmc_leg(n, args)
+        return
+    if args.pmc_leg == "splat3d":
+        pmc_splat3d_leg()
         return
     mu_h, nu_h = wl.config_c3(n)
     mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
@@ -520,7 +635,11 @@ def main():
                              "dual": rg.dual, "cap": args.gap_iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                     "kernel_ms": kt[dom], "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "kernel_ms": kt[dom], "algorithmic_bytes_per_launch": bytes_per_launch,
+                     # the whole iteration against the same peak: ITER_BYTES_PER_POINT per point
+                     "iteration_model_bytes_per_point": ITER_BYTES_PER_POINT[2],
+                     "iteration_achieved": ITER_BYTES_PER_POINT[2] * N / (dt / args.steps) / 1e9,
+                     "iteration_frac": ITER_BYTES_PER_POINT[2] * N / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kt,
         "tuning": tuning,
         "dual": r.dual,
@@ -540,6 +659,8 @@ def main():
         out["precision_c3"] = precision_leg(n, args.precision_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n)
+        if not args.no_oracle_legs:
+            out["oracle_legs"] = oracle_legs(args)
     print(json.dumps(out))
 
 

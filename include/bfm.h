@@ -94,7 +94,8 @@ typedef struct {
     int32_t iters;         /* completed full iterations */
     int32_t converged;     /* 1 when gap < tol stopped the loop */
     int32_t status;        /* bfm_status of the solve */
-    int32_t reserved;
+    int32_t sigma_floor_hits;  /* step-size updates (Section 4.2 rule) that left sigma at sigma_min:
+                                * the shrink branch was clamped there, or sigma stayed at it */
     double dual;           /* J(phi) = C(mu,nu) estimate = W2^2 / 2 */
     double primal;         /* int |x - T(x)|^2 / 2 dmu */
     double gap;
@@ -150,6 +151,25 @@ bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *
 bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *const *mu, const void *const *nu,
                              void *const *phi, void *const *psi, void *const *T, void *const *workspaces,
                              const size_t *ws_bytes, int32_t iters_per_graph, void *stream, bfm_result *results);
+
+/* Gradients of W2^2 for a batch of converged pairs (the bfm_grad formula for
+ * every pair: grad_mu = scale[p] * 2 cell_volume (psi - mean psi),
+ * grad_nu = scale[p] * 2 cell_volume (phi - mean phi); first variation of J,
+ * Lemma fact:derivative-J, envelope form), computed by three launches for the
+ * whole batch (potential sums per workgroup, the means per pair, the scaled
+ * differences) instead of four per pair.
+ *   plans       npairs plans (any shapes, one dtype).
+ *   phi, psi    host arrays of npairs device pointers: each pair's potentials,
+ *               N elements each (e.g. the outputs of bfm_solve_batched).
+ *   scale       host array of npairs factors (e.g. the upstream gradients).
+ *   grad_mu, grad_nu  host arrays of npairs device outputs of N elements, or
+ *               NULL (that gradient is not computed); NULL entries allowed.
+ *   workspaces  host array of npairs distinct device workspaces (overwritten).
+ * BFM_EINVAL for NULL arrays, mixed dtypes, a non-finite scale or shared
+ * workspaces; BFM_EWORKSPACE as in bfm_solve.  Synchronises `stream`. */
+bfm_status bfm_grad_batched(int32_t npairs, const bfm_plan *plans, const void *const *phi, const void *const *psi,
+                            const double *scale, void *const *grad_mu, void *const *grad_nu,
+                            void *const *workspaces, const size_t *ws_bytes, void *stream);
 
 /* Autotuner: times the candidate launch shapes of the c-transform line
  * kernel for every axis of the plan (points per lane 4, 8 or 16; on strided

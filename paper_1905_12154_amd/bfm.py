@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
-            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass", "bfm_interpolate"]
+            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass", "bfm_interpolate",
+            "bfm_grad_batched"]
 
 
 class BFMError(RuntimeError):
@@ -46,7 +47,7 @@ METHODS = {"bfm": 0, "ga": 1}
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("dual", ctypes.c_double), ("primal", ctypes.c_double),
+                ("sigma_floor_hits", ctypes.c_int32), ("dual", ctypes.c_double), ("primal", ctypes.c_double),
                 ("gap", ctypes.c_double), ("G", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("mass_mu", ctypes.c_double), ("mass_nu", ctypes.c_double)]
 
@@ -87,6 +88,7 @@ def lib():
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
                                         P(Result)]
         L.bfm_trace.argtypes = [vp, vp, sz, P(dbl), i32, P(i32), vp]
+        L.bfm_grad_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(dbl), P(vp), P(vp), P(vp), P(sz), vp]
         L.bfm_last_error.argtypes = []
         L.bfm_last_error.restype = ctypes.c_char_p
         L.bfm_version.argtypes = []
@@ -204,7 +206,7 @@ class Plan:
                                _ptr(ws), self.ws_bytes, _stream(dev), ctypes.byref(res)))
         return SolveResult(phi=phi, psi=psi, T=T, dual=res.dual, primal=res.primal, gap=res.gap, G=res.G,
                            sigma=res.sigma, iters=res.iters, converged=bool(res.converged),
-                           mass_mu=res.mass_mu, mass_nu=res.mass_nu)
+                           mass_mu=res.mass_mu, mass_nu=res.mass_nu, sigma_floor_hits=res.sigma_floor_hits)
 
     def autotune(self, device="cuda:0", sample: Optional[torch.Tensor] = None):
         """Time the c-transform launch shapes per axis (on ``sample``, a
@@ -328,6 +330,7 @@ class SolveResult:
     converged: bool
     mass_mu: float
     mass_nu: float
+    sigma_floor_hits: int = 0   # step-rule updates that left sigma at sigma_min
 
     @property
     def w2sq(self) -> float:
@@ -375,7 +378,7 @@ def poisson_neumann(f: torch.Tensor):
 def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_iters: int = 100,
                   tol: float = 0.0, iters_per_graph: int = 8, return_map: bool = False,
                   workspaces: Optional[List[torch.Tensor]] = None, method: str = "bfm",
-                  power: Optional[Sequence[float]] = None) -> List[SolveResult]:
+                  power: Optional[Sequence[float]] = None, aligned: bool = False) -> List[SolveResult]:
     """Solve many independent problems together (``bfm_solve_batched``): one
     HIP graph replay advances every problem by ``iters_per_graph`` iterations.
     Problems may have different shapes; all share dtype and ``max_iters``."""
@@ -390,11 +393,14 @@ def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_
     psis = [torch.empty_like(m) for m in mus]
     Ts = [torch.empty((len(p.shape),) + p.shape, dtype=p.dtype, device=dev) for p in plans] if return_map else None
     if workspaces is None:
-        workspaces = [torch.empty(p.ws_bytes + 256, dtype=torch.uint8, device=dev) for p in plans]
-    ws = []
-    for p, raw in zip(plans, workspaces):
-        off = (-raw.data_ptr()) % 256
-        ws.append(raw[off:off + p.ws_bytes])
+        ws = _aligned_workspaces(plans, dev)
+    elif aligned:   # already 256-byte aligned views of ws_bytes each
+        ws = list(workspaces)
+    else:
+        ws = []
+        for p, raw in zip(plans, workspaces):
+            off = (-raw.data_ptr()) % 256
+            ws.append(raw[off:off + p.ws_bytes])
     VP = ctypes.c_void_p * n
     res = (Result * n)()
     _check(lib().bfm_solve_batched(
@@ -407,35 +413,67 @@ def solve_batched(mus: Sequence[torch.Tensor], nus: Sequence[torch.Tensor], max_
         r = res[i]
         out.append(SolveResult(phi=phis[i], psi=psis[i], T=Ts[i] if Ts is not None else None, dual=r.dual,
                                primal=r.primal, gap=r.gap, G=r.G, sigma=r.sigma, iters=r.iters,
-                               converged=bool(r.converged), mass_mu=r.mass_mu, mass_nu=r.mass_nu))
+                               converged=bool(r.converged), mass_mu=r.mass_mu, mass_nu=r.mass_nu,
+                               sigma_floor_hits=r.sigma_floor_hits))
+    return out
+
+
+def grad_batched(plans: Sequence[Plan], phis: Sequence[torch.Tensor], psis: Sequence[torch.Tensor],
+                 scales: Sequence[float], workspaces: Sequence[torch.Tensor]):
+    """Gradients of W2^2 for a batch of solved pairs (``bfm_grad_batched``):
+    three launches for the whole batch; returns (grad_mu list, grad_nu list)."""
+    n = len(plans)
+    if not (len(phis) == len(psis) == len(scales) == len(workspaces) == n) or n == 0:
+        raise ValueError("need the same positive number of plans, potentials, scales and workspaces")
+    phis = [p._field(t, "phi[%d]" % i) for i, (p, t) in enumerate(zip(plans, phis))]
+    psis = [p._field(t, "psi[%d]" % i) for i, (p, t) in enumerate(zip(plans, psis))]
+    gmus = [torch.empty_like(t) for t in psis]
+    gnus = [torch.empty_like(t) for t in phis]
+    VP = ctypes.c_void_p * n
+    _check(lib().bfm_grad_batched(
+        n, VP(*[p.handle.value for p in plans]), VP(*[t.data_ptr() for t in phis]), VP(*[t.data_ptr() for t in psis]),
+        (ctypes.c_double * n)(*[float(x) for x in scales]), VP(*[t.data_ptr() for t in gmus]),
+        VP(*[t.data_ptr() for t in gnus]), VP(*[w.data_ptr() for w in workspaces]),
+        (ctypes.c_size_t * n)(*[p.ws_bytes for p in plans]), _stream(phis[0].device)))
+    return gmus, gnus
+
+
+def _aligned_workspaces(plans, dev):
+    out = []
+    for p in plans:
+        raw = torch.empty(p.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        out.append(raw[off:off + p.ws_bytes])
     return out
 
 
 class W2LossBatched(torch.autograd.Function):
     """W2^2 of many (mu_i, nu_i) pairs from one batched solve; the backward
-    pass returns each pair's mean-zeroed potentials times 2 cell_volume."""
+    pass returns each pair's mean-zeroed potentials times 2 cell_volume, for
+    the whole batch at once (bfm_grad_batched) on the solve's workspaces."""
 
     @staticmethod
     def forward(ctx, max_iters, tol, iters_per_graph, *tensors):
         n = len(tensors) // 2
         mus, nus = tensors[:n], tensors[n:]
+        dev = mus[0].device
+        # the plans solve_batched looks up (same keys), so the workspaces fit them
+        plans = [plan_for(m.shape, m.dtype, max_iters=max_iters, tol=tol, method="bfm", power=None) for m in mus]
+        ws = _aligned_workspaces(plans, dev)
         rs = solve_batched([m.detach() for m in mus], [v.detach() for v in nus], max_iters=max_iters, tol=tol,
-                           iters_per_graph=iters_per_graph)
-        ctx.plans = [plan_for(m.shape, m.dtype) for m in mus]
+                           iters_per_graph=iters_per_graph, workspaces=ws, aligned=True)
+        ctx.plans = plans
+        ctx.workspaces = ws
         ctx.save_for_backward(*[r.phi for r in rs], *[r.psi for r in rs])
         ctx.results = [(r.iters, r.converged, r.gap) for r in rs]
-        return torch.tensor([r.w2sq for r in rs], dtype=mus[0].dtype, device=mus[0].device)
+        return torch.tensor([r.w2sq for r in rs], dtype=mus[0].dtype, device=dev)
 
     @staticmethod
     def backward(ctx, grad_out):
         saved = ctx.saved_tensors
         n = len(saved) // 2
         go = grad_out.detach().double().cpu().tolist()
-        gmus, gnus = [], []
-        for i in range(n):
-            gmu, gnu = ctx.plans[i].grad(saved[i], saved[n + i], go[i])
-            gmus.append(gmu)
-            gnus.append(gnu)
+        gmus, gnus = grad_batched(ctx.plans, saved[:n], saved[n:], go, ctx.workspaces)
         return (None, None, None, *gmus, *gnus)
 
 

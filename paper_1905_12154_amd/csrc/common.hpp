@@ -48,6 +48,7 @@ struct DevState {
     int32_t done;                // 1: gap < tol reached, later kernels are no-ops
     int32_t nonfinite;           // 1: a non-finite scalar appeared
     int32_t ntrace;
+    int32_t sigma_floor_hits;    // step-rule updates that held sigma at sigma_min
 };
 
 // One trace record per evaluated head of a phi-step.

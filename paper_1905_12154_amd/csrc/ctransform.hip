@@ -111,38 +111,52 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                                              int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
 {
     const T n2 = T(n) * T(n);
-    // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
-    //    entries live in registers (u holds the lane's values), so only pops
-    //    read LDS.  Each push also links the element below it forward
-    //    (a later push over the same element overwrites a popped successor),
-    //    so the forward links of the final stack need no second walk.
+    // 2. lane-local lower hull of points [j0, j1): a stack scan.  The stack's
+    //    point offsets live in one 64-bit register (4 bits each, top in the
+    //    low bits) and the values of its top two entries in registers, so a
+    //    pop reads no link from LDS: one load of the new second value, whose
+    //    address is known at once.  The links of the final stack are written
+    //    once at the end.
     if (j0 < j1) {
-        int top = j0, a = -1;
-        T utop = u[0], ua = T(0);
-        pv[padi(j0)] = kNone;
+        static_assert(C <= 16, "4-bit stack offsets");
+        uint64_t stk = 0;   // offset 0 on top
+        int depth = 1;
+        T utop = u[0], ua = T(0);   // values of the top two entries
 #pragma unroll
         for (int c = 1; c < C; ++c) {
-            const int j = j0 + c;
-            if (j < j1) {
+            if (j0 + c < j1) {
                 const T uj = u[c];
-                while (a >= 0 && above_chord(a, top, j, ua, utop, uj, n2)) {
-                    pv[padi(top)] = kDead;
-                    top = a;
+                while (depth >= 2 &&
+                       above_chord(j0 + (int)((stk >> 4) & 15), j0 + (int)(stk & 15), j0 + c, ua, utop, uj, n2)) {
+                    stk >>= 4;
+                    --depth;
                     utop = ua;
-                    a = pv[padi(top)];
-                    if (a >= 0) ua = v[padi(a)];
+                    if (depth >= 2) ua = v[padi(j0 + (int)((stk >> 4) & 15))];
                 }
-                pv[padi(j)] = (short)top;
-                nx[padi(top)] = (short)j;
-                a = top;
                 ua = utop;
-                top = j;
                 utop = uj;
+                stk = (stk << 4) | (uint64_t)c;
+                ++depth;
             }
         }
-        nx[padi(top)] = kNone;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (j0 + c < j1) pv[padi(j0 + c)] = kDead;
         GH[t] = j0;
-        GT[t] = top;
+        GT[t] = j0 + (int)(stk & 15);
+        // from the top down: each entry links to the one above (nx) and below (pv)
+        uint64_t rest = stk;
+        int above = kNone;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            if (k < depth) {
+                const int j = j0 + (int)(rest & 15);
+                rest >>= 4;
+                nx[padi(j)] = (short)above;
+                pv[padi(j)] = k + 1 < depth ? (short)(j0 + (int)(rest & 15)) : kNone;
+                above = j;
+            }
+        }
     } else {
         GH[t] = -1;
         GT[t] = -1;
@@ -410,7 +424,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
 // in that layout, so every group's output is one contiguous 16 R-byte run;
 // the contiguous pass over the rows (nlines = R, n = K) reads it.
 template <typename T, int C, int LPB, bool STRIDED, bool BLK>
-__global__ void __launch_bounds__(ct_max_threads(C, LPB))
+__global__ void __launch_bounds__(ct_max_threads(C, LPB), 4)
 ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
                    T sgn, T h, const int32_t *__restrict__ done, const T *__restrict__ dotw,
                    double *__restrict__ dotpart)
@@ -772,6 +786,229 @@ hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *d
     }
     return hipSuccess;
 }
+
+// ------------------------------------------------------------ multi-pair
+// One pass of the 2D transform for every pair of a batch in one launch
+// (rows: u = -p into F; columns: F into p^c or q, the latter with the fused
+// sum of q * src).  Workgroups of 256 lanes, C = 16 points per lane, tpl
+// lanes per line (the next power of two >= n / 16) and 256 / tpl lines per
+// workgroup, so every pair's lines fill whole workgroups whatever its size.
+constexpr int kMultiCtThreads = 256;
+constexpr int kMultiCtC = 16;
+
+__host__ __device__ inline int multi_tpl(int n)
+{
+    int tpl = 1;
+    while (tpl * kMultiCtC < n) tpl <<= 1;
+    return tpl;
+}
+
+int ct_multi_col_groups(int n0, int n1)
+{
+    const int lpb = kMultiCtThreads / multi_tpl(n0);
+    return (n1 + lpb - 1) / lpb;
+}
+
+static int ct_multi_groups(int n0, int n1, bool strided)
+{
+    if (strided) return ct_multi_col_groups(n0, n1);
+    const int lpb = kMultiCtThreads / multi_tpl(n1);
+    return (n0 + lpb - 1) / lpb;
+}
+
+__device__ __forceinline__ int batch_pair(const BatchIdx &bi)
+{
+    int lo = 0, hi = bi.np - 1;   // largest p with off[p] <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bi.off[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// which: 0 head rows, 1 head columns, 2 step rows, 3 step columns (+ sum)
+template <typename T, bool STRIDED>
+__global__ void __launch_bounds__(kMultiCtThreads)
+ct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role, int which)
+{
+    constexpr int C = kMultiCtC;
+    using V4 = typename vec4<T>::type;
+    const int pr = batch_pair(bi);
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[pr];
+    if (P.st->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wave_tot[16];
+    __shared__ double dred[kMultiCtThreads / kWave];
+
+    const T *pfield = (const T *)(role ? P.psi : P.phi);
+    const T *src = (const T *)(role ? P.nu : P.mu);
+    const T *in = STRIDED ? (const T *)P.F : pfield;
+    T *out = STRIDED ? (which == 3 ? (T *)(role ? P.phi : P.psi) : (T *)P.pc) : (T *)P.F;
+    const T sgn = STRIDED ? T(1) : T(-1);
+    const bool dot = STRIDED && which == 3;
+
+    const int n = STRIDED ? P.n0 : P.n1;
+    const int inner = STRIDED ? P.n1 : 1;
+    const long long nlines = STRIDED ? P.n1 : P.n0;
+    const int tpl = multi_tpl(n);
+    const int lpb = kMultiCtThreads / tpl;
+    const int NP = padded_len(n);
+    T *vals = reinterpret_cast<T *>(smem);                                   // [lpb][NP]
+    short *links = reinterpret_cast<short *>(vals + (size_t)lpb * NP);        // [lpb][2][NP]
+    int *grp = reinterpret_cast<int *>(smem + ((((size_t)lpb * NP * sizeof(T) + (size_t)lpb * 2 * NP * sizeof(short)) + 3) & ~(size_t)3));
+
+    const int tid = threadIdx.x;
+    const long long L0 = (long long)(blockIdx.x - bi.off[pr]) * lpb;
+    const int l = tid / tpl, t = tid - l * tpl;
+    const long long L = L0 + l;
+    const int j0 = t * C, j1 = min(j0 + C, n);
+    T *v = vals + l * NP;
+    short *pv = links + (size_t)l * 2 * NP;
+    int *GH = grp + l * 2 * tpl;
+
+    T u[C];
+    if (!STRIDED) {
+        const T *row = in + L * n;
+#pragma unroll
+        for (int q = 0; q < C; q += 4) {
+            if (L < nlines && j0 + q < n) {   // n % 4 == 0
+                const V4 x = *reinterpret_cast<const V4 *>(row + j0 + q);
+                u[q] = x.x; u[q + 1] = x.y; u[q + 2] = x.z; u[q + 3] = x.w;
+            } else {
+                u[q] = u[q + 1] = u[q + 2] = u[q + 3] = T(0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            u[c] *= sgn;
+            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+        }
+    } else {
+        // lines L0 .. L0 + lpb - 1 are adjacent columns: four per 16-byte
+        // vector of a grid row (lpb >= 4), else element by element
+        if (lpb >= 4) {
+            const int nv = lpb / 4;
+            for (int e = tid; e < nv * n; e += kMultiCtThreads) {
+                const int vq = e % nv, j = e / nv;
+                const long long c0 = L0 + 4 * vq;
+                V4 x;
+                if (c0 < nlines) x = *reinterpret_cast<const V4 *>(in + (long long)j * inner + c0);
+                else x.x = x.y = x.z = x.w = T(0);
+                const int pj = padi(j);
+                vals[(4 * vq + 0) * NP + pj] = sgn * x.x;
+                vals[(4 * vq + 1) * NP + pj] = sgn * x.y;
+                vals[(4 * vq + 2) * NP + pj] = sgn * x.z;
+                vals[(4 * vq + 3) * NP + pj] = sgn * x.w;
+            }
+        } else {
+            for (int e = tid; e < lpb * n; e += kMultiCtThreads) {
+                const int ll = e % lpb, j = e / lpb;
+                const long long c = L0 + ll;
+                vals[ll * NP + padi(j)] = c < nlines ? sgn * in[(long long)j * inner + c] : T(0);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
+    }
+
+    ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, T(1.0) / T(n));
+
+    double dacc = 0.0;
+    if (!STRIDED) {
+        if (L < nlines && j0 < j1) {
+            T *dst = out + L * n;
+#pragma unroll
+            for (int q = 0; q < C; q += 4) {
+                if (j0 + q < n) {
+                    V4 x;
+                    x.x = u[q]; x.y = u[q + 1]; x.z = u[q + 2]; x.w = u[q + 3];
+                    *reinterpret_cast<V4 *>(dst + j0 + q) = x;
+                }
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+        __syncthreads();
+        if (lpb >= 4) {
+            const int nv = lpb / 4;
+            for (int e = tid; e < nv * n; e += kMultiCtThreads) {
+                const int vq = e % nv, j = e / nv;
+                const long long c0 = L0 + 4 * vq;
+                if (c0 >= nlines) continue;
+                const int pj = padi(j);
+                V4 x;
+                x.x = vals[(4 * vq + 0) * NP + pj];
+                x.y = vals[(4 * vq + 1) * NP + pj];
+                x.z = vals[(4 * vq + 2) * NP + pj];
+                x.w = vals[(4 * vq + 3) * NP + pj];
+                const long long at = (long long)j * inner + c0;
+                *reinterpret_cast<V4 *>(out + at) = x;
+                if (dot) {
+                    const V4 w = *reinterpret_cast<const V4 *>(src + at);
+                    dacc += (double)x.x * w.x + (double)x.y * w.y + (double)x.z * w.z + (double)x.w * w.w;
+                }
+            }
+        } else {
+            for (int e = tid; e < lpb * n; e += kMultiCtThreads) {
+                const int ll = e % lpb, j = e / lpb;
+                const long long c = L0 + ll;
+                if (c >= nlines) continue;
+                const long long at = (long long)j * inner + c;
+                const T x = vals[ll * NP + padi(j)];
+                out[at] = x;
+                if (dot) dacc += (double)x * src[at];
+            }
+        }
+    }
+    if (dot) {   // uniform: one partial per workgroup of the pair, in group order
+        dacc = wave_sum(dacc);
+        if ((tid & (kWave - 1)) == 0) dred[tid / kWave] = dacc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < kMultiCtThreads / kWave; ++w) sum += dred[w];
+            P.part[S_Q_SRC * P.slot_len + (blockIdx.x - bi.off[pr])] = sum;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_ct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int which,
+                           hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk || which < 0 || which > 3) return hipErrorInvalidValue;
+    const bool strided = (which & 1) != 0;
+    BatchIdx bi{};
+    bi.np = np;
+    size_t smem = 0;
+    for (int p = 0; p < np; ++p) {
+        const int n = strided ? n0s[p] : n1s[p];
+        if (n > kMultiCtC * kMultiCtThreads || (n1s[p] & 3) != 0) return hipErrorInvalidValue;
+        const int tpl = multi_tpl(n);
+        const size_t b = ct_smem_for(n, tpl, kMultiCtThreads / tpl, sizeof(T));
+        smem = b > smem ? b : smem;
+        bi.off[p + 1] = bi.off[p] + ct_multi_groups(n0s[p], n1s[p], strided);
+    }
+    static size_t lds_limit[2][kMaxDevices] = {};
+    const void *fn = strided ? (const void *)ct_multi_kernel<T, true> : (const void *)ct_multi_kernel<T, false>;
+    hipError_t e = raise_dyn_lds(fn, smem, lds_limit[strided ? 1 : 0]);
+    if (e != hipSuccess) return e;
+    if (strided)
+        hipLaunchKernelGGL((ct_multi_kernel<T, true>), dim3((unsigned)bi.off[np]), dim3(kMultiCtThreads), smem, stream,
+                           tab, bi, role, which);
+    else
+        hipLaunchKernelGGL((ct_multi_kernel<T, false>), dim3((unsigned)bi.off[np]), dim3(kMultiCtThreads), smem,
+                           stream, tab, bi, role, which);
+    return hipGetLastError();
+}
+
+template hipError_t launch_ct_multi<float>(const BatchHead *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_ct_multi<double>(const BatchHead *, const int *, const int *, int, int, int, hipStream_t);
 
 template hipError_t launch_ct_axis<float>(const float *, float *, int, int, long long, float, const int32_t *,
                                           hipStream_t, CtCfg);

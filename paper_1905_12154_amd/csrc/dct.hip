@@ -242,7 +242,7 @@ struct DctArgs {
     int innerB;              // line index = kA * nB + kB
 };
 
-enum DctMode { DM_FWD = 0, DM_INV = 1, DM_FUSED = 2 };
+enum DctMode { DM_FWD = kDctFwd, DM_INV = kDctInv, DM_FUSED = kDctFused };
 
 // After a forward FFT of z = v_a + i v_b in buf, the DCT-II coefficients of
 // lines a and b at index k.
@@ -287,14 +287,16 @@ __device__ __forceinline__ double block_sum_any(double v, double *sh) {
 // Line transforms along one axis.  NPAIR pairs of lines (2 NPAIR lines) per
 // workgroup, bd lanes per pair.  CONTIG: lines are contiguous (axis ndim-1,
 // NPAIR = 1); otherwise four adjacent lines are read/written as 16-byte vectors.
+// The body of one workgroup: line group `blk` (2 NPAIR lines from line
+// 2 NPAIR blk); the workgroup's float64 partial (G, or the sum with dotw)
+// goes to *gslot.
 template <typename T, int VMAX, int NPAIR, int MODE, bool CONTIG>
-__global__ void __launch_bounds__(512)
-dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, DctArgs ax, int zero_b,
-                 const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw, const T *__restrict__ lam0,
-                 const T *__restrict__ lamA, const T *__restrict__ lamB, double *__restrict__ gpart,
-                 const T *__restrict__ dotw, const int32_t *__restrict__ done)
+__device__ __forceinline__ void
+dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, const DctArgs &ax, int zero_b,
+               const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw, const T *__restrict__ lam0,
+               const T *__restrict__ lamA, const T *__restrict__ lamB, double *__restrict__ gslot,
+               const T *__restrict__ dotw, long long blk)
 {
-    if (done != nullptr && *done) return;
     // Vector loads per thread (the launch guarantees n <= 16 bd): contiguous
     // lines take n / (4 bd) <= 4 per line, the two-pair strided form
     // n / (2 bd) <= 8.  Each load loop issues all of them before the first
@@ -307,7 +309,6 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
     const int bd = blockDim.x / NPAIR;
     const int pr = threadIdx.x / bd, lt = threadIdx.x - pr * bd;
     cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem) + (size_t)pr * NPC;
-    const long long blk = xcd_map(blockIdx.x, gridDim.x);
     const long long L0 = blk * (2 * NPAIR);          // first line of the workgroup
     const long long La = L0 + 2 * pr, Lb = La + 1;   // this pair
     const bool hasa = La < ax.nlines, hasb = Lb < ax.nlines;
@@ -725,9 +726,69 @@ dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, D
     }
     if (MODE == DM_FUSED || (MODE == DM_INV && CONTIG && dotw != nullptr)) {   // uniform
         const double gs = block_sum_any(gacc, red);
-        if (threadIdx.x == 0) gpart[blockIdx.x] = gs;
+        if (threadIdx.x == 0) *gslot = gs;
     }
 }
+
+template <typename T, int VMAX, int NPAIR, int MODE, bool CONTIG>
+__global__ void __launch_bounds__(512)
+dct_lines_kernel(const T *a, T *b, T *out, const T *base, const double *scale, DctArgs ax, int zero_b,
+                 const cpx<T> *__restrict__ tw, const cpx<T> *__restrict__ qw, const T *__restrict__ lam0,
+                 const T *__restrict__ lamA, const T *__restrict__ lamB, double *__restrict__ gpart,
+                 const T *__restrict__ dotw, const int32_t *__restrict__ done)
+{
+    if (done != nullptr && *done) return;
+    dct_lines_body<T, VMAX, NPAIR, MODE, CONTIG>(a, b, out, base, scale, ax, zero_b, tw, qw, lam0, lamA, lamB,
+                                                 gpart != nullptr ? gpart + blockIdx.x : nullptr, dotw,
+                                                 xcd_map(blockIdx.x, gridDim.x));
+}
+
+// ------------------------------------------------------------ multi-pair
+// One pass of the 2D Poisson solve for every pair of a batch in one launch:
+//   DM_FWD:   rows of tgt - rho into F (rho cleared), axis 1;
+//   DM_FUSED: columns of F forward, divided by lambda, G partials, inverse;
+//   DM_INV:   rows of F back, p += sigma g, partials of sum p * tgt.
+// role 0 is the phi-step (p, tgt) = (phi, nu), role 1 the psi-step (psi, mu).
+// Partials go to the pair's own slots at the workgroup's index inside the pair.
+template <typename T, int NPAIR, int MODE, bool CONTIG>
+__global__ void __launch_bounds__(512)
+dct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role)
+{
+    int lo = 0, hi = bi.np - 1;   // largest pair with off[pair] <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bi.off[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[lo];
+    if (P.st->done) return;
+    const long long blk = (long long)blockIdx.x - bi.off[lo];
+    T *p = (T *)(role ? P.psi : P.phi);
+    const T *tgt = (const T *)(role ? P.mu : P.nu);
+    const int ax_ = MODE == DM_FUSED ? 0 : 1;
+    DctArgs ax{};
+    ax.n = ax_ == 0 ? P.n0 : P.n1;
+    ax.inner = ax_ == 0 ? P.n1 : 1;
+    ax.nlines = ax_ == 0 ? P.n1 : P.n0;
+    ax.radices = P.radices[ax_];
+    ax.nA = P.n1;
+    ax.nB = 1;
+    ax.innerB = 1;
+    const cpx<T> *tw = (const cpx<T> *)(P.tables + P.tw[ax_]);
+    const cpx<T> *qw = (const cpx<T> *)(P.tables + P.qw[ax_]);
+    if (MODE == DM_FWD)
+        dct_lines_body<T, 16, NPAIR, MODE, CONTIG>(tgt, (T *)P.rho, (T *)P.F, nullptr, nullptr, ax, 1, tw, qw, nullptr,
+                                                   nullptr, nullptr, nullptr, nullptr, blk);
+    else if (MODE == DM_FUSED)
+        dct_lines_body<T, 16, NPAIR, MODE, CONTIG>((T *)P.F, nullptr, (T *)P.F, nullptr, nullptr, ax, 0, tw, qw,
+                                                   (const T *)(P.tables + P.lam[0]), (const T *)(P.tables + P.lam[1]),
+                                                   nullptr, P.gpart + blk, nullptr, blk);
+    else
+        dct_lines_body<T, 16, NPAIR, MODE, CONTIG>((T *)P.F, nullptr, p, p, &P.st->sigma, ax, 0, tw, qw, nullptr,
+                                                   nullptr, nullptr, P.part + S_Q_TGT * P.slot_len + blk, tgt, blk);
+}
+
+long long dct_multi_inv_parts(int n0) { return (n0 + 1) / 2; }
 
 static int dct_block(int n) {
     int bd = 64;
@@ -833,6 +894,48 @@ long long dct_fused_parts(int n0, long long N, size_t esz)
     return two ? (nl + 3) / 4 : (nl + 1) / 2;
 }
 
+template <typename T>
+hipError_t launch_dct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int mode,
+                            hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
+    BatchIdx bi{};
+    bi.np = np;
+    int bd = 64, nmax = 1;
+    for (int p = 0; p < np; ++p) {
+        const int n = mode == DM_FUSED ? n0s[p] : n1s[p];
+        if ((n1s[p] & 3) != 0) return hipErrorInvalidValue;
+        const int b = dct_block(n);
+        bd = b > bd ? b : bd;
+        nmax = n > nmax ? n : nmax;
+        const long long lines = mode == DM_FUSED ? n1s[p] : n0s[p];
+        bi.off[p + 1] = bi.off[p] + (int)(mode == DM_FUSED ? (lines + 3) / 4 : (lines + 1) / 2);
+    }
+    const int npair = mode == DM_FUSED ? 2 : 1;
+    if (bd * npair > 512) return hipErrorInvalidValue;
+    const size_t smem = (size_t)npair * padc_len(nmax) * sizeof(cpx<T>);
+    static size_t lds_limit[3][kMaxDevices] = {};
+    const dim3 grid((unsigned)bi.off[np]), block(bd * npair);
+    hipError_t e = hipSuccess;
+    if (mode == DM_FWD) {
+        e = raise_dyn_lds((const void *)dct_multi_kernel<T, 1, DM_FWD, true>, smem, lds_limit[0]);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((dct_multi_kernel<T, 1, DM_FWD, true>), grid, block, smem, stream, tab, bi, role);
+    } else if (mode == DM_FUSED) {
+        e = raise_dyn_lds((const void *)dct_multi_kernel<T, 2, DM_FUSED, false>, smem, lds_limit[1]);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((dct_multi_kernel<T, 2, DM_FUSED, false>), grid, block, smem, stream, tab, bi, role);
+    } else if (mode == DM_INV) {
+        e = raise_dyn_lds((const void *)dct_multi_kernel<T, 1, DM_INV, true>, smem, lds_limit[2]);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL((dct_multi_kernel<T, 1, DM_INV, true>), grid, block, smem, stream, tab, bi, role);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 #define BFM_INST_DCT(T)                                                                                       \
     template hipError_t launch_dct_fwd<T>(const T *, T *, T *, const AxisPlan &, long long, int, const void *, \
                                           const void *, const int32_t *, hipStream_t);                         \
@@ -844,5 +947,7 @@ long long dct_fused_parts(int n0, long long N, size_t esz)
                                             const int32_t *, hipStream_t);
 BFM_INST_DCT(float)
 BFM_INST_DCT(double)
+template hipError_t launch_dct_multi<float>(const BatchHead *, const int *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_dct_multi<double>(const BatchHead *, const int *, const int *, int, int, int, hipStream_t);
 
 }  // namespace bfm

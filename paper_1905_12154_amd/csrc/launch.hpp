@@ -157,4 +157,83 @@ struct CtrlParams {
 hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,
                        TraceRec *trace, hipStream_t stream);
 
+// ------------------------------------------------------------ multi-pair
+// Batched form: many independent 2D problems advanced by one launch per pass.
+// The pairs of one launch (at most kBatchChunk) are described by a device
+// table of PairDev records (kept in the workspace of the chunk's first
+// pair); each launch also takes, by value, the prefix of its workgroups per
+// pair (BatchIdx), so a workgroup finds its pair by a binary search over
+// kernel arguments.
+constexpr int kBatchChunk = 64;
+constexpr int kBatchSplatGrid = 2048;   // workgroups of the joint deposition
+
+struct PairDev {
+    const void *mu, *nu;
+    void *phi, *psi;
+    void *pc, *rho, *F;
+    DevState *st;
+    TraceRec *trace;
+    double *part;        // kNumSlots slots of slot_len float64 partials
+    double *gpart;       // partials of G from the fused Poisson pass
+    const unsigned char *tables;
+    const int *tiles_mu, *tiles_nu;   // count, then the tiles of mu / nu that hold mass
+    long long slot_len;
+    int n0, n1;
+    int tw[2], qw[2], lam[2];   // byte offsets of the axis tables in `tables`
+    uint32_t radices[2];
+    int ent_mu, ent_nu;         // first entry of the pair in the joint deposition lists (device-filled)
+    CtrlParams cp;              // controller parameters with the multi-pair partial counts
+};
+// Table header in device memory, followed by the PairDev records.
+struct BatchHead {
+    int np;
+    int ent_total_mu, ent_total_nu;   // lengths of the joint deposition lists (device-filled)
+    int all_done;                     // 1 when every pair's stop flag is set (launch_batch_done)
+};
+constexpr size_t kBatchTableBytes = sizeof(BatchHead) + kBatchChunk * sizeof(PairDev);
+
+struct BatchIdx {
+    int np;
+    int off[kBatchChunk + 1];   // first workgroup of each pair; off[np] = grid size
+};
+
+// role 0: the phi-step (p, src, tgt, q) = (phi, mu, nu, psi); role 1: the
+// psi-step (psi, nu, mu, phi).  Every launch skips pairs whose stop flag is set.
+enum MultiCt { MCT_HEAD = 0, MCT_STEP = 1 };
+template <typename T>
+hipError_t launch_ct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int which,
+                           hipStream_t stream);
+template <typename T>
+hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, hipStream_t stream);
+hipError_t launch_batch_entries(BatchHead *tab, hipStream_t stream);
+// modes of launch_dct_multi (the DCT pass kinds of dct.hip)
+constexpr int kDctFwd = 0, kDctInv = 1, kDctFused = 2;
+template <typename T>
+hipError_t launch_dct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int mode,
+                            hipStream_t stream);
+hipError_t launch_ctrl_multi(const BatchHead *tab, int np, int role, int mode, hipStream_t stream);
+hipError_t launch_batch_done(BatchHead *tab, hipStream_t stream);
+// Batched W2^2 gradient: per pair, the potentials' sums (one partial per
+// workgroup into S_MEAN_A (psi) and S_MEAN_B (phi)), the means (one workgroup
+// per pair), then gmu = mul (psi - mean psi), gnu = mul (phi - mean phi).
+struct GradPair {
+    const void *phi, *psi;
+    void *gmu, *gnu;     // either may be null
+    DevState *st;
+    double *part;
+    long long slot_len;
+    long long N;
+    long long epb;       // elements per workgroup (a multiple of 4 * kRedBlock)
+    int nb;              // workgroups of the pair
+    double mul;          // 2 cell_volume scale
+};
+constexpr size_t kGradTableBytes = kBatchChunk * sizeof(GradPair);
+static_assert(kGradTableBytes <= kBatchTableBytes, "gradient table fits the batch region");
+template <typename T>
+hipError_t launch_grad_multi(const GradPair *tab, const GradPair *host, int np, hipStream_t stream);
+
+// partial counts the multi-pair launches leave per pair (for CtrlParams)
+int ct_multi_col_groups(int n0, int n1);
+long long dct_multi_inv_parts(int n0);
+
 }  // namespace bfm

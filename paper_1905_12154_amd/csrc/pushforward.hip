@@ -99,40 +99,19 @@ template <typename T> __device__ __forceinline__ T tpow(T x, T y) {
         return pow(x, y);
 }
 
+// One source tile: map, partial sums, deposition through the LDS box.  All
+// lanes of the workgroup call it with the same tile (its barriers are
+// uniform).  `box` is all zero on entry and on return; `bnd` holds the two
+// alternating bound sets, `kused` counts the tiles with mass processed so far.
 template <typename T, int D, bool GEN>
-__global__ void __launch_bounds__(kRedBlock)
-splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
-             T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
-             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done, T tmix,
-             const int *__restrict__ tiles)
+__device__ __forceinline__ void
+splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)[D], long long tile,
+           const T *__restrict__ pc, const T *__restrict__ src, T *__restrict__ rho, T *__restrict__ Tout, T tmix,
+           T *box, int (*bnd)[2 * D], int &kused, double &accP, double &accJ)
 {
-    if (done != nullptr && *done) return;
     constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
     constexpr int kBoxCap = box_cap<T, D>();
-    __shared__ double sh[kRedBlock / kWave];
-    __shared__ T box[kBoxCap];
-    __shared__ int bnd[2][2 * D];   // box bounds, alternating between consecutive tiles with mass
-
-    int ntile[D];
-    T pw[D], ex[D];   // exponent p_a of the cost and 1 / (p_a - 1)
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
-        pw[a] = T(g.pw[a]);
-        ex[a] = T(1.0 / (g.pw[a] - 1.0));
-    }
-    double accP = 0.0, accJ = 0.0;
-    for (int e = threadIdx.x; e < kBoxCap; e += kRedBlock) box[e] = T(0);
-    if (threadIdx.x < 2 * D) {
-        bnd[threadIdx.x / D][threadIdx.x % D] = 0x7fffffff;
-        bnd[threadIdx.x / D][D + threadIdx.x % D] = -1;
-    }
-    __syncthreads();
-    int kused = 0;   // tiles with mass processed so far by this workgroup
-
-    const long long count = tiles != nullptr ? (long long)tiles[0] : ntiles_total;
-    for (long long k = blockIdx.x; k < count; k += gridDim.x) {
-        const long long tile = tiles != nullptr ? (long long)tiles[1 + k] : k;
+    {
         int tc[D];
         long long rem = tile;
 #pragma unroll
@@ -161,7 +140,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             s[q] = inside ? src[id] : T(0);
             any = any || s[q] != T(0);
         }
-        if (!__syncthreads_or(any) && Tout == nullptr) continue;
+        if (!__syncthreads_or(any) && Tout == nullptr) return;
         // this tile's bounds; the other set was last read before the barrier
         // above, so it is reset here for the next tile
         int *bb = bnd[kused & 1];
@@ -277,7 +256,7 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
             }
         }
         __syncthreads();
-        if (rho == nullptr || bb[D] < 0) continue;   // uniform: read after the barrier
+        if (rho == nullptr || bb[D] < 0) return;   // uniform: read after the barrier
         int bl[D], bs[D];
         long long area = 1;
 #pragma unroll
@@ -341,12 +320,161 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
         // no barrier: the next tile deposits into the box only after its own
         // two barriers, which this flush precedes
     }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void splat_setup(const Grid &g, int (&ntile)[D], T (&pw)[D], T (&ex)[D])
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
+        pw[a] = T(g.pw[a]);
+        ex[a] = T(1.0 / (g.pw[a] - 1.0));
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void splat_clear(T *box, int (*bnd)[2 * D])
+{
+    for (int e = threadIdx.x; e < box_cap<T, D>(); e += kRedBlock) box[e] = T(0);
+    if (threadIdx.x < 2 * D) {
+        bnd[threadIdx.x / D][threadIdx.x % D] = 0x7fffffff;
+        bnd[threadIdx.x / D][D + threadIdx.x % D] = -1;
+    }
+    __syncthreads();
+}
+
+template <typename T, int D, bool GEN>
+__global__ void __launch_bounds__(kRedBlock)
+splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *__restrict__ src,
+             T *__restrict__ rho, T *__restrict__ Tout, double *__restrict__ part_primal,
+             double *__restrict__ part_pcsrc, const int32_t *__restrict__ done, T tmix,
+             const int *__restrict__ tiles)
+{
+    if (done != nullptr && *done) return;
+    __shared__ double sh[kRedBlock / kWave];
+    __shared__ T box[box_cap<T, D>()];
+    __shared__ int bnd[2][2 * D];   // box bounds, alternating between consecutive tiles with mass
+    int ntile[D];
+    T pw[D], ex[D];   // exponent p_a of the cost and 1 / (p_a - 1)
+    splat_setup<T, D>(g, ntile, pw, ex);
+    double accP = 0.0, accJ = 0.0;
+    splat_clear<T, D>(box, bnd);
+    int kused = 0;   // tiles with mass processed so far by this workgroup
+    const long long count = tiles != nullptr ? (long long)tiles[0] : ntiles_total;
+    for (long long k = blockIdx.x; k < count; k += gridDim.x) {
+        const long long tile = tiles != nullptr ? (long long)tiles[1 + k] : k;
+        splat_tile<T, D, GEN>(g, ntile, pw, ex, tile, pc, src, rho, Tout, tmix, box, bnd, kused, accP, accJ);
+    }
     const double P = block_reduce<R_SUM>(accP, sh);
     const double J = block_reduce<R_SUM>(accJ, sh);
     if (threadIdx.x == 0) {
         if (part_primal != nullptr) part_primal[blockIdx.x] = P;
         if (part_pcsrc != nullptr) part_pcsrc[blockIdx.x] = J;
     }
+}
+
+// ------------------------------------------------------------ multi-pair
+// The deposition of every pair of a batch (2D, quadratic cost) in one launch:
+// the pairs' lists of tiles with mass are walked as one joint list (pair p's
+// entries start at ent_mu / ent_nu), kBatchSplatGrid workgroups striding
+// over it.  A workgroup keeps its sums per pair and writes them when its walk
+// leaves the pair, at index (first entry it visited - the pair's first
+// entry): the pair's partials are then indices 0 .. min(grid, entries) - 1.
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock)
+splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
+{
+    constexpr int D = 2;
+    __shared__ double sh[kRedBlock / kWave];
+    __shared__ T box[box_cap<T, D>()];
+    __shared__ int bnd[2][2 * D];
+    const PairDev *pairs = reinterpret_cast<const PairDev *>(tab + 1);
+    const int np = tab->np;
+    const int total = role ? tab->ent_total_nu : tab->ent_total_mu;
+    splat_clear<T, D>(box, bnd);
+    int kused = 0, cur = -1;
+    double accP = 0.0, accJ = 0.0;
+    long long first = 0;
+    Grid g{};
+    int ntile[D];
+    T pw[D], ex[D];
+    const T *pc = nullptr, *src = nullptr;
+    T *rho = nullptr;
+    const int *tiles = nullptr;
+    bool skip = false;
+    auto flush = [&]() {
+        const double P = block_reduce<R_SUM>(accP, sh);
+        const double J = block_reduce<R_SUM>(accJ, sh);
+        if (threadIdx.x == 0 && !skip) {
+            const PairDev &Q = pairs[cur];
+            const long long i = first - (role ? Q.ent_nu : Q.ent_mu);
+            Q.part[S_PRIMAL * Q.slot_len + i] = P;
+            Q.part[S_PC_SRC * Q.slot_len + i] = J;
+        }
+        accP = accJ = 0.0;
+    };
+    for (long long k = blockIdx.x; k < total; k += gridDim.x) {
+        int p = cur < 0 ? 0 : cur;
+        while (p + 1 < np && (role ? pairs[p + 1].ent_nu : pairs[p + 1].ent_mu) <= k) ++p;
+        if (p != cur) {
+            if (cur >= 0) flush();
+            cur = p;
+            first = k;
+            const PairDev &Q = pairs[p];
+            skip = Q.st->done != 0;
+            g.ndim = 2;
+            g.n[0] = Q.n0;
+            g.n[1] = Q.n1;
+            g.n[2] = 1;
+            g.stride[0] = Q.n1;
+            g.stride[1] = 1;
+            g.stride[2] = 0;
+            g.N = (long long)Q.n0 * Q.n1;
+            g.vol = 1.0 / (double)g.N;
+            g.pw[0] = g.pw[1] = g.pw[2] = 2.0;
+            splat_setup<T, D>(g, ntile, pw, ex);
+            pc = (const T *)Q.pc;
+            src = (const T *)(role ? Q.nu : Q.mu);
+            rho = (T *)Q.rho;
+            tiles = role ? Q.tiles_nu : Q.tiles_mu;
+        }
+        if (skip) continue;   // uniform: the pair has stopped
+        const long long tile = tiles[1 + (k - (role ? pairs[p].ent_nu : pairs[p].ent_mu))];
+        splat_tile<T, D, false>(g, ntile, pw, ex, tile, pc, src, rho, nullptr, T(1), box, bnd, kused, accP, accJ);
+    }
+    if (cur >= 0) flush();
+}
+
+// Joint-list offsets of the pairs' deposition tiles (one lane: at most
+// kBatchChunk pairs).
+__global__ void batch_entries_kernel(BatchHead *tab)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    PairDev *pairs = reinterpret_cast<PairDev *>(tab + 1);
+    int am = 0, an = 0;
+    for (int p = 0; p < tab->np; ++p) {
+        pairs[p].ent_mu = am;
+        pairs[p].ent_nu = an;
+        am += pairs[p].tiles_mu[0];
+        an += pairs[p].tiles_nu[0];
+    }
+    tab->ent_total_mu = am;
+    tab->ent_total_nu = an;
+}
+
+hipError_t launch_batch_entries(BatchHead *tab, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_entries_kernel, dim3(1), dim3(64), 0, stream, tab);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((splat_multi_kernel<T>), dim3(kBatchSplatGrid), dim3(kRedBlock), 0, stream, tab, role);
+    return hipGetLastError();
 }
 
 template <int D> long long splat_tiles(const Grid &g) {
@@ -480,6 +608,8 @@ template hipError_t launch_splat<float>(const Grid &, const float *, const float
 template hipError_t launch_splat<double>(const Grid &, const double *, const double *, double *, double *,
                                          double *, double *, int, const int32_t *, hipStream_t, double, const int *);
 template hipError_t launch_tile_list<float>(const Grid &, const float *, int *, int *, hipStream_t);
+template hipError_t launch_splat_multi<float>(const BatchHead *, int, int, hipStream_t);
+template hipError_t launch_splat_multi<double>(const BatchHead *, int, int, hipStream_t);
 template hipError_t launch_tile_list<double>(const Grid &, const double *, int *, int *, hipStream_t);
 
 }  // namespace bfm

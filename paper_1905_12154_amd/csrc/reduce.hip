@@ -226,9 +226,9 @@ __device__ double step_rule(double sigma, double increase, double G, const CtrlP
     return sigma;
 }
 
-__global__ void __launch_bounds__(kRedBlock)
-ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__restrict__ gpart, int mode,
-            CtrlParams prm, TraceRec *trace)
+__device__ __forceinline__ void ctrl_body(DevState *st, const double *__restrict__ partials,
+                                          const double *__restrict__ gpart, int mode, const CtrlParams &prm,
+                                          TraceRec *trace)
 {
     __shared__ double sh[4 * (kRedBlock / kWave)];
     const int nb = prm.nred, ns = prm.nsplat, ng = prm.ngpart;
@@ -259,6 +259,7 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
             st->done = 0;
             st->nonfinite = 0;
             st->ntrace = 0;
+            st->sigma_floor_hits = 0;
         }
         return;
     }
@@ -348,10 +349,133 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
                     trace[tr].I_new = st->J_new;
             }
             st->sigma = step_rule(st->sigma, st->J_new - st->J_old, st->G, prm);
+            if (st->sigma == prm.sigma_min) st->sigma_floor_hits += 1;
             if (mode == CTRL_STEP_PSI) st->iter += 1;
         }
     }
 }
+
+__global__ void __launch_bounds__(kRedBlock)
+ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__restrict__ gpart, int mode,
+            CtrlParams prm, TraceRec *trace)
+{
+    ctrl_body(st, partials, gpart, mode, prm, trace);
+}
+
+// The controller of every pair of a batch: one workgroup per pair, each with
+// its pair's state, partials and counts (the deposition's partial count is
+// the number of its joint-list workgroups that visited the pair).
+__global__ void __launch_bounds__(kRedBlock)
+ctrl_multi_kernel(const BatchHead *__restrict__ tab, int role, int mode)
+{
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[blockIdx.x];
+    CtrlParams prm = P.cp;
+    const int ent = (role ? P.tiles_nu : P.tiles_mu)[0];
+    prm.nsplat = ent < kBatchSplatGrid ? ent : kBatchSplatGrid;
+    ctrl_body(P.st, P.part, P.gpart, mode, prm, P.trace);
+}
+
+__global__ void batch_done_kernel(BatchHead *tab)
+{
+    const PairDev *pairs = reinterpret_cast<const PairDev *>(tab + 1);
+    int all = 1;
+    for (int p = threadIdx.x; p < tab->np; p += blockDim.x) all &= pairs[p].st->done != 0;
+    all = __syncthreads_and(all);
+    if (threadIdx.x == 0) tab->all_done = all;
+}
+
+hipError_t launch_batch_done(BatchHead *tab, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_done_kernel, dim3(1), dim3(kWave), 0, stream, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_multi(const BatchHead *tab, int np, int role, int mode, hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ctrl_multi_kernel, dim3(np), dim3(kRedBlock), 0, stream, tab, role, mode);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched gradient
+__device__ __forceinline__ int grad_pair_of(const BatchIdx &bi)
+{
+    int lo = 0, hi = bi.np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bi.off[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) grad_sums_kernel(const GradPair *__restrict__ tab, BatchIdx bi)
+{
+    __shared__ double sh[kRedBlock / kWave];
+    const int p = grad_pair_of(bi);
+    const GradPair &G = tab[p];
+    const long long b = (long long)blockIdx.x - bi.off[p];
+    const long long i0 = b * G.epb, i1 = i0 + G.epb < G.N ? i0 + G.epb : G.N;
+    const T *phi = (const T *)G.phi, *psi = (const T *)G.psi;
+    double sa = 0.0, sb = 0.0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += kRedBlock) {
+        sa += (double)psi[i];
+        sb += (double)phi[i];
+    }
+    sa = block_reduce<R_SUM>(sa, sh);
+    sb = block_reduce<R_SUM>(sb, sh);
+    if (threadIdx.x == 0) {
+        G.part[S_MEAN_A * G.slot_len + b] = sa;
+        G.part[S_MEAN_B * G.slot_len + b] = sb;
+    }
+}
+
+__global__ void __launch_bounds__(kRedBlock) grad_means_kernel(const GradPair *__restrict__ tab)
+{
+    __shared__ double sh[4 * (kRedBlock / kWave)];
+    const GradPair &G = tab[blockIdx.x];
+    const double a = slot_reduce_sum(G.part, G.slot_len, S_MEAN_A, G.nb, sh);
+    const double b = slot_reduce_sum(G.part, G.slot_len, S_MEAN_B, G.nb, sh);
+    if (threadIdx.x == 0) {
+        G.st->mean_a = a / (double)G.N;
+        G.st->mean_b = b / (double)G.N;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) grad_apply_kernel(const GradPair *__restrict__ tab, BatchIdx bi)
+{
+    const int p = grad_pair_of(bi);
+    const GradPair &G = tab[p];
+    const long long b = (long long)blockIdx.x - bi.off[p];
+    const long long i0 = b * G.epb, i1 = i0 + G.epb < G.N ? i0 + G.epb : G.N;
+    const T ca = T(-G.st->mean_a), cb = T(-G.st->mean_b), m = T(G.mul);
+    const T *phi = (const T *)G.phi, *psi = (const T *)G.psi;
+    T *gmu = (T *)G.gmu, *gnu = (T *)G.gnu;
+    for (long long i = i0 + threadIdx.x; i < i1; i += kRedBlock) {
+        if (gmu != nullptr) gmu[i] = m * (psi[i] + ca);
+        if (gnu != nullptr) gnu[i] = m * (phi[i] + cb);
+    }
+}
+
+template <typename T>
+hipError_t launch_grad_multi(const GradPair *tab, const GradPair *host, int np, hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
+    BatchIdx bi{};
+    bi.np = np;
+    for (int p = 0; p < np; ++p) bi.off[p + 1] = bi.off[p] + host[p].nb;
+    hipLaunchKernelGGL((grad_sums_kernel<T>), dim3((unsigned)bi.off[np]), dim3(kRedBlock), 0, stream, tab, bi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_means_kernel, dim3(np), dim3(kRedBlock), 0, stream, tab);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((grad_apply_kernel<T>), dim3((unsigned)bi.off[np]), dim3(kRedBlock), 0, stream, tab, bi);
+    return hipGetLastError();
+}
+template hipError_t launch_grad_multi<float>(const GradPair *, const GradPair *, int, hipStream_t);
+template hipError_t launch_grad_multi<double>(const GradPair *, const GradPair *, int, hipStream_t);
 
 hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,
                        TraceRec *trace, hipStream_t stream)

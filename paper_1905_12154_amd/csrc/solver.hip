@@ -59,6 +59,7 @@ struct bfm_plan_s {
     // workspace layout (byte offsets from the workspace base)
     size_t off_state, off_trace, off_part, off_gpart, off_tables, off_pc, off_rho, off_f, total;
     size_t off_tiles_mu, off_tiles_nu;   // deposition tiles of mu and nu that hold mass
+    size_t off_batch;                    // multi-pair table of a batch led by this pair
     long long ntiles;
     size_t tab_tw[3], tab_qw[3], tab_lam[3];   // offsets inside the table image
     std::vector<unsigned char> tables;         // host image of the spectral tables
@@ -227,6 +228,7 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     P->ntiles = splat_tile_count(g);
     P->off_tiles_mu = off; off = align256(off + sizeof(int) * (size_t)(P->ntiles + 1));
     P->off_tiles_nu = off; off = align256(off + sizeof(int) * (size_t)(P->ntiles + 1));
+    P->off_batch = off;    off = align256(off + kBatchTableBytes);
     const size_t fb = align256((size_t)g.N * P->esz);
     P->off_pc = off;  off += fb;
     P->off_rho = off; off += fb;
@@ -255,6 +257,7 @@ struct Ws {
     unsigned char *tables;
     void *pc, *rho, *f;
     int *tiles_mu, *tiles_nu;   // filled by solve_begin
+    BatchHead *batch;           // multi-pair table (batched solves led by this pair)
     long long slot_len;
     double *slot(int s) const { return part + (size_t)s * slot_len; }
 };
@@ -277,6 +280,7 @@ static bfm_status check_ws(bfm_plan P, void *ws, size_t ws_bytes, Ws *w)
     w->f = b + P->off_f;
     w->tiles_mu = (int *)(b + P->off_tiles_mu);
     w->tiles_nu = (int *)(b + P->off_tiles_nu);
+    w->batch = (BatchHead *)(b + P->off_batch);
     return BFM_OK;
 }
 
@@ -551,6 +555,7 @@ static bfm_status fill_result(const DevState &hs, bfm_result *res)
         res->iters = hs.iter;
         res->converged = (hs.done && !hs.nonfinite) ? 1 : 0;
         res->status = hs.nonfinite ? BFM_ENUMERIC : BFM_OK;
+        res->sigma_floor_hits = hs.sigma_floor_hits;
         res->dual = hs.dual_head;
         res->primal = hs.primal_head;
         res->gap = hs.gap;
@@ -737,6 +742,201 @@ static bfm_status batched_impl(int np, const bfm_plan *P, const void *const *mu_
     return out;
 }
 
+// ------------------------------------------------- batched, one launch per pass
+// 2D quadratic-cost batches: after the first iteration (enqueued per pair),
+// every pass of a half-step runs as ONE launch over all pairs of a chunk of
+// at most kBatchChunk pairs (c-transform rows and columns, deposition, the
+// three Poisson passes, the controller), reading a device table of per-pair
+// pointers and sizes; K iterations of these launches are captured once into
+// a graph and replayed.  Each pair keeps its own step size, gap and stop
+// flag; a stopped pair's workgroups return at once.
+static bool multi_applies(int np, const bfm_plan *P)
+{
+    for (int p = 0; p < np; ++p) {
+        const Grid &g = P[p]->g;
+        if (g.ndim != 2 || !grid_quadratic(g) || P[p]->prm.method != BFM_METHOD_BFM) return false;
+        if ((g.n[1] & 3) != 0) return false;
+    }
+    return true;
+}
+
+namespace {
+struct MultiChunk {
+    int first = 0, np = 0;
+    BatchHead *tab = nullptr;     // device table in the workspace of pair `first`
+    std::vector<int> n0, n1;
+};
+}  // namespace
+
+template <typename T>
+static hipError_t multi_half_step(const MultiChunk &c, int role, hipStream_t s)
+{
+    const int np = c.np;
+    const int head = role ? CTRL_HEAD_PSI : CTRL_HEAD_PHI, step = role ? CTRL_STEP_PSI : CTRL_STEP_PHI;
+    hipError_t e;
+    if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 0, s)) != hipSuccess) return e;
+    if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 1, s)) != hipSuccess) return e;
+    if ((e = launch_splat_multi<T>(c.tab, np, role, s)) != hipSuccess) return e;
+    if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFwd, s)) != hipSuccess) return e;
+    if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFused, s)) != hipSuccess) return e;
+    if ((e = launch_ctrl_multi(c.tab, np, role, head | CTRL_REUSE_DOT, s)) != hipSuccess) return e;
+    if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctInv, s)) != hipSuccess) return e;
+    if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 2, s)) != hipSuccess) return e;
+    if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 3, s)) != hipSuccess) return e;
+    return launch_ctrl_multi(c.tab, np, role, step, s);
+}
+
+template <typename T>
+static hipError_t multi_iterations(const std::vector<MultiChunk> &chunks, int count, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < count && e == hipSuccess; ++it)
+        for (int role = 0; role < 2 && e == hipSuccess; ++role)
+            for (const MultiChunk &c : chunks)
+                if ((e = multi_half_step<T>(c, role, s)) != hipSuccess) break;
+    for (const MultiChunk &c : chunks)
+        if (e == hipSuccess) e = launch_batch_done(c.tab, s);
+    return e;
+}
+
+template <typename T>
+static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *const *mu_, const void *const *nu_,
+                                     void *const *phi_, void *const *psi_, void *const *T_, const std::vector<Ws> &w,
+                                     int K, hipStream_t s, bfm_result *res)
+{
+    auto MU = [&](int p) { return (const T *)mu_[p]; };
+    auto NU = [&](int p) { return (const T *)nu_[p]; };
+    auto PHI = [&](int p) { return (T *)phi_[p]; };
+    auto PSI = [&](int p) { return (T *)psi_[p]; };
+    std::vector<DevState> hs(np);
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = solve_begin<T>(P[p], MU(p), NU(p), nullptr, PHI(p), w[p], s, false);
+        if (st != BFM_OK) return st;
+    }
+    for (int p = 0; p < np; ++p)
+        HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = check_inputs(hs[p]);
+        if (st != BFM_OK) return fail(st, "pair %d: %s", p, g_last_error.c_str());
+    }
+    // device tables, one per chunk of pairs
+    std::vector<MultiChunk> chunks;
+    std::vector<std::vector<unsigned char>> images;
+    for (int first = 0; first < np; first += kBatchChunk) {
+        MultiChunk c;
+        c.first = first;
+        c.np = np - first < kBatchChunk ? np - first : kBatchChunk;
+        c.tab = w[first].batch;
+        std::vector<unsigned char> img(sizeof(BatchHead) + (size_t)c.np * sizeof(PairDev), 0);
+        BatchHead hd{};
+        hd.np = c.np;
+        memcpy(img.data(), &hd, sizeof(hd));
+        for (int k = 0; k < c.np; ++k) {
+            const int p = first + k;
+            const bfm_plan_s *Q = P[p];
+            const Ws &W = w[p];
+            PairDev d{};
+            d.mu = mu_[p];
+            d.nu = nu_[p];
+            d.phi = phi_[p];
+            d.psi = psi_[p];
+            d.pc = W.pc;
+            d.rho = W.rho;
+            d.F = W.f;
+            d.st = W.st;
+            d.trace = W.trace;
+            d.part = W.part;
+            d.gpart = W.gpart;
+            d.tables = W.tables;
+            d.tiles_mu = W.tiles_mu;
+            d.tiles_nu = W.tiles_nu;
+            d.slot_len = W.slot_len;
+            d.n0 = Q->g.n[0];
+            d.n1 = Q->g.n[1];
+            for (int a = 0; a < 2; ++a) {
+                d.tw[a] = (int)Q->tab_tw[a];
+                d.qw[a] = (int)Q->tab_qw[a];
+                d.lam[a] = (int)Q->tab_lam[a];
+                d.radices[a] = Q->ax[a].radices;
+            }
+            d.cp = ctrl_params(const_cast<bfm_plan>(Q));
+            d.cp.nqt = (int)dct_multi_inv_parts(d.n0);
+            d.cp.nqs = ct_multi_col_groups(d.n0, d.n1);
+            if (d.cp.nqt > W.slot_len || d.cp.nqs > W.slot_len || (d.n1 + 3) / 4 != Q->gparts)
+                return fail(BFM_EDEVICE, "pair %d: multi-pair partial counts exceed the workspace slots", p);
+            memcpy(img.data() + sizeof(BatchHead) + (size_t)k * sizeof(PairDev), &d, sizeof(d));
+            c.n0.push_back(d.n0);
+            c.n1.push_back(d.n1);
+        }
+        chunks.push_back(c);
+        images.push_back(std::move(img));
+    }
+    for (size_t i = 0; i < chunks.size(); ++i) {
+        HIP_TRY(hipMemcpyAsync(chunks[i].tab, images[i].data(), images[i].size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_batch_entries(chunks[i].tab, s));
+    }
+    auto all_done = [&](bool *out) -> bfm_status {
+        std::vector<BatchHead> h(chunks.size());
+        for (size_t i = 0; i < chunks.size(); ++i)
+            HIP_TRY(hipMemcpyAsync(&h[i], chunks[i].tab, sizeof(BatchHead), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *out = true;
+        for (const BatchHead &x : h) *out = *out && x.all_done != 0;
+        return BFM_OK;
+    };
+    const int maxit = P[0]->prm.max_iters;
+    int it = 0;
+    bool done = false;
+    if (maxit > 0) {   // the first iteration per pair: its heads compute <p, tgt> directly
+        for (int p = 0; p < np; ++p)
+            HIP_TRY(enqueue_iterations<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), 0, 1, s));
+        it = 1;
+    }
+    if (maxit - it >= K) {
+        hipStream_t cap = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+            ce = multi_iterations<T>(chunks, K, cap);
+            hipError_t ee = hipStreamEndCapture(cap, &graph);
+            if (ce == hipSuccess) ce = ee;
+        }
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        bfm_status bst = BFM_OK;
+        while (ce == hipSuccess && bst == BFM_OK && maxit - it >= K) {
+            ce = hipGraphLaunch(exec, s);
+            it += K;
+            if (ce == hipSuccess) bst = all_done(&done);
+            if (done) break;
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        HIP_TRY(ce);
+        if (bst != BFM_OK) return bst;
+    }
+    if (!done && it < maxit) {
+        HIP_TRY(multi_iterations<T>(chunks, maxit - it, s));
+        it = maxit;
+    }
+    for (int p = 0; p < np; ++p) {
+        HIP_TRY(enqueue_final_head<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), it, s));
+        HIP_TRY(enqueue_finish<T>(P[p], w[p], MU(p), PHI(p), PSI(p), T_ != nullptr ? (T *)T_[p] : nullptr, s));
+    }
+    for (int p = 0; p < np; ++p)
+        HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bfm_status out = BFM_OK;
+    for (int p = 0; p < np; ++p) {
+        bfm_status st = fill_result(hs[p], res != nullptr ? &res[p] : nullptr);
+        if (st != BFM_OK && out == BFM_OK) out = st;
+    }
+    return out;
+}
+
 extern "C" bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, const void *const *mu,
                                         const void *const *nu, void *const *phi, void *const *psi, void *const *T,
                                         void *const *workspaces, const size_t *ws_bytes, int32_t iters_per_graph,
@@ -762,9 +962,65 @@ extern "C" bfm_status bfm_solve_batched(int32_t npairs, const bfm_plan *plans, c
             if (workspaces[q] == workspaces[p]) return fail(BFM_EINVAL, "pairs %d and %d share a workspace", q, p);
     }
     hipStream_t s = (hipStream_t)stream;
+    const bool multi = multi_applies(npairs, plans);
     if (plans[0]->prm.dtype == BFM_F64)
-        return batched_impl<double>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
-    return batched_impl<float>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
+        return multi ? batched_multi_impl<double>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results)
+                     : batched_impl<double>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
+    return multi ? batched_multi_impl<float>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results)
+                 : batched_impl<float>(npairs, plans, mu, nu, phi, psi, T, w, iters_per_graph, s, results);
+}
+
+// ------------------------------------------------------- batched gradient
+
+extern "C" bfm_status bfm_grad_batched(int32_t npairs, const bfm_plan *plans, const void *const *phi,
+                                       const void *const *psi, const double *scale, void *const *grad_mu,
+                                       void *const *grad_nu, void *const *workspaces, const size_t *ws_bytes,
+                                       void *stream)
+{
+    if (npairs < 1) return fail(BFM_EINVAL, "npairs must be >= 1");
+    if (plans == nullptr || phi == nullptr || psi == nullptr || scale == nullptr || workspaces == nullptr ||
+        ws_bytes == nullptr)
+        return fail(BFM_EINVAL, "NULL argument");
+    std::vector<Ws> w(npairs);
+    std::vector<GradPair> g(npairs);
+    for (int p = 0; p < npairs; ++p) {
+        if (plans[p] == nullptr) return fail(BFM_EINVAL, "plan %d is NULL", p);
+        if (plans[p]->prm.dtype != plans[0]->prm.dtype) return fail(BFM_EINVAL, "pair %d: dtype differs", p);
+        if (phi[p] == nullptr || psi[p] == nullptr) return fail(BFM_EINVAL, "pair %d: NULL potential", p);
+        if (!isfinite(scale[p])) return fail(BFM_EINVAL, "pair %d: scale must be finite", p);
+        bfm_status st = check_ws(plans[p], workspaces[p], ws_bytes[p], &w[p]);
+        if (st != BFM_OK) return fail(st, "pair %d: %s", p, g_last_error.c_str());
+        for (int q = 0; q < p; ++q)
+            if (workspaces[q] == workspaces[p]) return fail(BFM_EINVAL, "pairs %d and %d share a workspace", q, p);
+        const bfm_plan_s *P = plans[p];
+        GradPair &G = g[p];
+        G.phi = phi[p];
+        G.psi = psi[p];
+        G.gmu = grad_mu != nullptr ? grad_mu[p] : nullptr;
+        G.gnu = grad_nu != nullptr ? grad_nu[p] : nullptr;
+        G.st = w[p].st;
+        G.part = w[p].part;
+        G.slot_len = w[p].slot_len;
+        G.N = P->g.N;
+        long long epb = 4 * kRedBlock;
+        while ((G.N + epb - 1) / epb > G.slot_len) epb += 4 * kRedBlock;
+        G.epb = epb;
+        G.nb = (int)((G.N + epb - 1) / epb);
+        G.mul = 2.0 * P->g.vol * scale[p];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int first = 0; first < npairs; first += kBatchChunk) {
+        const int np = npairs - first < kBatchChunk ? npairs - first : kBatchChunk;
+        GradPair *tab = reinterpret_cast<GradPair *>(w[first].batch);
+        HIP_TRY(hipMemcpyAsync(tab, g.data() + first, (size_t)np * sizeof(GradPair), hipMemcpyHostToDevice, s));
+        if (plans[0]->prm.dtype == BFM_F64)
+            HIP_TRY(launch_grad_multi<double>(tab, g.data() + first, np, s));
+        else
+            HIP_TRY(launch_grad_multi<float>(tab, g.data() + first, np, s));
+    }
+    // the host table must outlive the copies above
+    HIP_TRY(hipStreamSynchronize(s));
+    return BFM_OK;
 }
 
 // ------------------------------------------------------------ autotuner

@@ -140,3 +140,23 @@ def test_header_is_plain_c():
     r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", "c", hdr],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_grad_batched_validation_before_any_launch():
+    L = bfm.lib()
+    plan = bfm.Plan((32, 32), dtype="float64")
+    VP = ctypes.c_void_p * 2
+    ws_ok = [0x100000, 0x100000 + ((plan.ws_bytes + 255) // 256) * 256]
+    f = VP(0x1000, 0x2000)
+    plans = VP(plan.handle.value, plan.handle.value)
+    sizes = (ctypes.c_size_t * 2)(plan.ws_bytes, plan.ws_bytes)
+    ones = (ctypes.c_double * 2)(1.0, 1.0)
+    assert L.bfm_grad_batched(0, plans, f, f, ones, f, f, VP(*ws_ok), sizes, None) == bfm.BFM_EINVAL
+    assert L.bfm_grad_batched(2, plans, None, f, ones, f, f, VP(*ws_ok), sizes, None) == bfm.BFM_EINVAL
+    bad = (ctypes.c_double * 2)(1.0, float("nan"))
+    assert L.bfm_grad_batched(2, plans, f, f, bad, f, f, VP(*ws_ok), sizes, None) == bfm.BFM_EINVAL
+    assert "scale" in L.bfm_last_error().decode()
+    shared = VP(ws_ok[0], ws_ok[0])
+    assert L.bfm_grad_batched(2, plans, f, f, ones, f, f, shared, sizes, None) == bfm.BFM_EINVAL
+    small = (ctypes.c_size_t * 2)(plan.ws_bytes, plan.ws_bytes - 1)
+    assert L.bfm_grad_batched(2, plans, f, f, ones, f, f, VP(*ws_ok), small, None) == bfm.BFM_EWORKSPACE
