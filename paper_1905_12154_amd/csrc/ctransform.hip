@@ -111,52 +111,38 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                                              int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
 {
     const T n2 = T(n) * T(n);
-    // 2. lane-local lower hull of points [j0, j1): a stack scan.  The stack's
-    //    point offsets live in one 64-bit register (4 bits each, top in the
-    //    low bits) and the values of its top two entries in registers, so a
-    //    pop reads no link from LDS: one load of the new second value, whose
-    //    address is known at once.  The links of the final stack are written
-    //    once at the end.
+    // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
+    //    entries live in registers (u holds the lane's values), so only pops
+    //    read LDS.  Each push also links the element below it forward
+    //    (a later push over the same element overwrites a popped successor),
+    //    so the forward links of the final stack need no second walk.
     if (j0 < j1) {
-        static_assert(C <= 16, "4-bit stack offsets");
-        uint64_t stk = 0;   // offset 0 on top
-        int depth = 1;
-        T utop = u[0], ua = T(0);   // values of the top two entries
+        int top = j0, a = -1;
+        T utop = u[0], ua = T(0);
+        pv[padi(j0)] = kNone;
 #pragma unroll
         for (int c = 1; c < C; ++c) {
-            if (j0 + c < j1) {
+            const int j = j0 + c;
+            if (j < j1) {
                 const T uj = u[c];
-                while (depth >= 2 &&
-                       above_chord(j0 + (int)((stk >> 4) & 15), j0 + (int)(stk & 15), j0 + c, ua, utop, uj, n2)) {
-                    stk >>= 4;
-                    --depth;
+                while (a >= 0 && above_chord(a, top, j, ua, utop, uj, n2)) {
+                    pv[padi(top)] = kDead;
+                    top = a;
                     utop = ua;
-                    if (depth >= 2) ua = v[padi(j0 + (int)((stk >> 4) & 15))];
+                    a = pv[padi(top)];
+                    if (a >= 0) ua = v[padi(a)];
                 }
+                pv[padi(j)] = (short)top;
+                nx[padi(top)] = (short)j;
+                a = top;
                 ua = utop;
+                top = j;
                 utop = uj;
-                stk = (stk << 4) | (uint64_t)c;
-                ++depth;
             }
         }
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (j0 + c < j1) pv[padi(j0 + c)] = kDead;
+        nx[padi(top)] = kNone;
         GH[t] = j0;
-        GT[t] = j0 + (int)(stk & 15);
-        // from the top down: each entry links to the one above (nx) and below (pv)
-        uint64_t rest = stk;
-        int above = kNone;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            if (k < depth) {
-                const int j = j0 + (int)(rest & 15);
-                rest >>= 4;
-                nx[padi(j)] = (short)above;
-                pv[padi(j)] = k + 1 < depth ? (short)(j0 + (int)(rest & 15)) : kNone;
-                above = j;
-            }
-        }
+        GT[t] = top;
     } else {
         GH[t] = -1;
         GT[t] = -1;
@@ -424,7 +410,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
 // in that layout, so every group's output is one contiguous 16 R-byte run;
 // the contiguous pass over the rows (nlines = R, n = K) reads it.
 template <typename T, int C, int LPB, bool STRIDED, bool BLK>
-__global__ void __launch_bounds__(ct_max_threads(C, LPB), 4)
+__global__ void __launch_bounds__(ct_max_threads(C, LPB))
 ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner, long long nlines, int tpl,
                    T sgn, T h, const int32_t *__restrict__ done, const T *__restrict__ dotw,
                    double *__restrict__ dotpart)

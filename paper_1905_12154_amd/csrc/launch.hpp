@@ -183,6 +183,7 @@ struct PairDev {
     uint32_t radices[2];
     int ent_mu, ent_nu;         // first entry of the pair in the joint deposition lists (device-filled)
     CtrlParams cp;              // controller parameters with the multi-pair partial counts
+    void *Tmap;                 // map output (2 planar fields) or null
 };
 // Table header in device memory, followed by the PairDev records.
 struct BatchHead {
@@ -231,6 +232,16 @@ constexpr size_t kGradTableBytes = kBatchChunk * sizeof(GradPair);
 static_assert(kGradTableBytes <= kBatchTableBytes, "gradient table fits the batch region");
 template <typename T>
 hipError_t launch_grad_multi(const GradPair *tab, const GradPair *host, int np, hipStream_t stream);
+
+// The outputs of every pair after its last head: phi - mean(phi) and
+// phi^c + mean(phi) (three launches; epb elements per workgroup, chosen so
+// that no pair has more workgroups than its slots hold).
+template <typename T>
+hipError_t launch_finish_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, long long epb,
+                               hipStream_t stream);
+// T = x - grad phi^c of every pair with a map output (PairDev::Tmap)
+template <typename T>
+hipError_t launch_map_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, hipStream_t stream);
 
 // partial counts the multi-pair launches leave per pair (for CtrlParams)
 int ct_multi_col_groups(int n0, int n1);

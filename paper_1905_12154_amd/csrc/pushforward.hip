@@ -446,6 +446,63 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
     if (cur >= 0) flush();
 }
 
+// The map of every pair of a batch that has a map output (2D, quadratic
+// cost): T_a = x_a - d_a clamped to the cell-centre box, d by central
+// differences of phi^c (one-sided on the faces), with the same operations as
+// the deposition's map.  kMapCells cells per workgroup.
+constexpr int kMapCells = 4 * kRedBlock;
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) map_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi)
+{
+    int lo = 0, hi = bi.np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bi.off[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[lo];
+    const long long N = (long long)P.n0 * P.n1;
+    const long long c0 = ((long long)blockIdx.x - bi.off[lo]) * kMapCells;
+    const T *pc = (const T *)P.pc;
+    T *Tout = (T *)P.Tmap;
+    const int nn[2] = {P.n0, P.n1};
+    const long long str[2] = {P.n1, 1};
+    for (long long id = c0 + threadIdx.x; id < c0 + kMapCells && id < N; id += kRedBlock) {
+        const int ii[2] = {(int)(id / P.n1), (int)(id % P.n1)};
+        const T p0 = pc[id];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int n = nn[a], i = ii[a];
+            const T fn = T(n);
+            const T pp = pc[i + 1 < n ? id + str[a] : id], pm = pc[i > 0 ? id - str[a] : id];
+            T d;
+            if (i == 0)
+                d = (pp - p0) * fn;
+            else if (i == n - 1)
+                d = (p0 - pm) * fn;
+            else
+                d = (pp - pm) * (T(0.5) * fn);
+            const T x = (T(i) + T(0.5)) / fn;
+            const T lo_t = T(0.5) / fn;
+            Tout[(long long)a * N + id] = fmin(fmax(x - d, lo_t), T(1) - lo_t);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_map_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
+    BatchIdx bi{};
+    bi.np = np;
+    for (int p = 0; p < np; ++p)
+        bi.off[p + 1] = bi.off[p] + (n0s[p] > 0 ? (int)(((long long)n0s[p] * n1s[p] + kMapCells - 1) / kMapCells) : 0);
+    if (bi.off[np] == 0) return hipSuccess;
+    hipLaunchKernelGGL((map_multi_kernel<T>), dim3((unsigned)bi.off[np]), dim3(kRedBlock), 0, stream, tab, bi);
+    return hipGetLastError();
+}
+
 // Joint-list offsets of the pairs' deposition tiles (one lane: at most
 // kBatchChunk pairs).
 __global__ void batch_entries_kernel(BatchHead *tab)
@@ -609,6 +666,8 @@ template hipError_t launch_splat<double>(const Grid &, const double *, const dou
                                          double *, double *, int, const int32_t *, hipStream_t, double, const int *);
 template hipError_t launch_tile_list<float>(const Grid &, const float *, int *, int *, hipStream_t);
 template hipError_t launch_splat_multi<float>(const BatchHead *, int, int, hipStream_t);
+template hipError_t launch_map_multi<float>(const BatchHead *, const int *, const int *, int, hipStream_t);
+template hipError_t launch_map_multi<double>(const BatchHead *, const int *, const int *, int, hipStream_t);
 template hipError_t launch_splat_multi<double>(const BatchHead *, int, int, hipStream_t);
 template hipError_t launch_tile_list<double>(const Grid &, const double *, int *, int *, hipStream_t);
 

@@ -253,6 +253,7 @@ __device__ __forceinline__ void ctrl_body(DevState *st, const double *__restrict
             st->bad = bad;
             st->sigma = prm.sigma0 > 0.0 ? prm.sigma0 : 8.0 * fmin(1.0 / xmu, 1.0 / xnu);
             st->J_old = st->P = st->G = st->J_new = st->gap = 0.0;
+            st->q_src = 0.0;   // <phi_0, nu> of a start from phi_0 = 0 (a head reusing the step sum reads it)
             st->dual_head = st->primal_head = st->G_head = 0.0;
             st->mean_a = st->mean_b = 0.0;
             st->iter = 0;
@@ -476,6 +477,83 @@ hipError_t launch_grad_multi(const GradPair *tab, const GradPair *host, int np, 
 }
 template hipError_t launch_grad_multi<float>(const GradPair *, const GradPair *, int, hipStream_t);
 template hipError_t launch_grad_multi<double>(const GradPair *, const GradPair *, int, hipStream_t);
+
+// ------------------------------------------------------- batched finish
+// After the last head of every pair: phi <- phi - mean(phi) and
+// psi <- phi^c + mean(phi) (the outputs of a solve), for a chunk of pairs in
+// three launches: per-workgroup sums of phi, the mean per pair, the shifts.
+__device__ __forceinline__ void finish_range(const PairDev &P, long long b, long long epb, long long &i0,
+                                             long long &i1)
+{
+    const long long N = (long long)P.n0 * P.n1;
+    i0 = b * epb;
+    i1 = i0 + epb < N ? i0 + epb : N;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) finish_sums_kernel(const BatchHead *__restrict__ tab, BatchIdx bi,
+                                                                long long epb)
+{
+    __shared__ double sh[kRedBlock / kWave];
+    const int p = grad_pair_of(bi);
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[p];
+    const long long b = (long long)blockIdx.x - bi.off[p];
+    long long i0, i1;
+    finish_range(P, b, epb, i0, i1);
+    const T *phi = (const T *)P.phi;
+    double s = 0.0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += kRedBlock) s += (double)phi[i];
+    s = block_reduce<R_SUM>(s, sh);
+    if (threadIdx.x == 0) P.part[S_MEAN_A * P.slot_len + b] = s;
+}
+
+__global__ void __launch_bounds__(kRedBlock) finish_means_kernel(const BatchHead *__restrict__ tab, BatchIdx bi)
+{
+    __shared__ double sh[kRedBlock / kWave];
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[blockIdx.x];
+    const int nb = bi.off[blockIdx.x + 1] - bi.off[blockIdx.x];
+    const double a = slot_reduce_sum(P.part, P.slot_len, S_MEAN_A, nb, sh);
+    if (threadIdx.x == 0) P.st->mean_a = a / ((double)P.n0 * (double)P.n1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock) finish_apply_kernel(const BatchHead *__restrict__ tab, BatchIdx bi,
+                                                                 long long epb)
+{
+    const int p = grad_pair_of(bi);
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[p];
+    const long long b = (long long)blockIdx.x - bi.off[p];
+    long long i0, i1;
+    finish_range(P, b, epb, i0, i1);
+    const T m = T(P.st->mean_a);
+    T *phi = (T *)P.phi, *psi = (T *)P.psi;
+    const T *pc = (const T *)P.pc;
+    for (long long i = i0 + threadIdx.x; i < i1; i += kRedBlock) {
+        phi[i] = phi[i] - m;
+        psi[i] = pc[i] + m;
+    }
+}
+
+template <typename T>
+hipError_t launch_finish_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, long long epb,
+                               hipStream_t stream)
+{
+    if (np < 1 || np > kBatchChunk || epb < 1) return hipErrorInvalidValue;
+    BatchIdx bi{};
+    bi.np = np;
+    for (int p = 0; p < np; ++p) bi.off[p + 1] = bi.off[p] + (int)(((long long)n0s[p] * n1s[p] + epb - 1) / epb);
+    hipLaunchKernelGGL((finish_sums_kernel<T>), dim3((unsigned)bi.off[np]), dim3(kRedBlock), 0, stream, tab, bi, epb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finish_means_kernel, dim3(np), dim3(kRedBlock), 0, stream, tab, bi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((finish_apply_kernel<T>), dim3((unsigned)bi.off[np]), dim3(kRedBlock), 0, stream, tab, bi, epb);
+    return hipGetLastError();
+}
+template hipError_t launch_finish_multi<float>(const BatchHead *, const int *, const int *, int, long long,
+                                               hipStream_t);
+template hipError_t launch_finish_multi<double>(const BatchHead *, const int *, const int *, int, long long,
+                                                hipStream_t);
 
 hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart, int mode, CtrlParams prm,
                        TraceRec *trace, hipStream_t stream)

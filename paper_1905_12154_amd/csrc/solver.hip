@@ -765,21 +765,36 @@ struct MultiChunk {
     int first = 0, np = 0;
     BatchHead *tab = nullptr;     // device table in the workspace of pair `first`
     std::vector<int> n0, n1;
+    std::vector<int> n0map;       // n0 of the pairs with a map output, 0 for the others
+    long long epb = 0;            // elements per workgroup of the finishing passes
 };
 }  // namespace
 
+// The head of a half-step for every pair of a chunk: p^c, the map and
+// deposition, the forward Poisson passes, the controller (J, P, G, gap, stop
+// test).  <p, tgt> is the previous step's <q, src> (CTRL_REUSE_DOT); at the
+// first head phi_0 = 0 and the state holds 0 for it.
 template <typename T>
-static hipError_t multi_half_step(const MultiChunk &c, int role, hipStream_t s)
+static hipError_t multi_head(const MultiChunk &c, int role, hipStream_t s)
 {
     const int np = c.np;
-    const int head = role ? CTRL_HEAD_PSI : CTRL_HEAD_PHI, step = role ? CTRL_STEP_PSI : CTRL_STEP_PHI;
+    const int head = role ? CTRL_HEAD_PSI : CTRL_HEAD_PHI;
     hipError_t e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 0, s)) != hipSuccess) return e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 1, s)) != hipSuccess) return e;
     if ((e = launch_splat_multi<T>(c.tab, np, role, s)) != hipSuccess) return e;
     if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFwd, s)) != hipSuccess) return e;
     if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFused, s)) != hipSuccess) return e;
-    if ((e = launch_ctrl_multi(c.tab, np, role, head | CTRL_REUSE_DOT, s)) != hipSuccess) return e;
+    return launch_ctrl_multi(c.tab, np, role, head | CTRL_REUSE_DOT, s);
+}
+
+template <typename T>
+static hipError_t multi_half_step(const MultiChunk &c, int role, hipStream_t s)
+{
+    const int np = c.np;
+    const int step = role ? CTRL_STEP_PSI : CTRL_STEP_PHI;
+    hipError_t e;
+    if ((e = multi_head<T>(c, role, s)) != hipSuccess) return e;
     if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctInv, s)) != hipSuccess) return e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 2, s)) != hipSuccess) return e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 3, s)) != hipSuccess) return e;
@@ -807,7 +822,6 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
     auto MU = [&](int p) { return (const T *)mu_[p]; };
     auto NU = [&](int p) { return (const T *)nu_[p]; };
     auto PHI = [&](int p) { return (T *)phi_[p]; };
-    auto PSI = [&](int p) { return (T *)psi_[p]; };
     std::vector<DevState> hs(np);
     for (int p = 0; p < np; ++p) {
         bfm_status st = solve_begin<T>(P[p], MU(p), NU(p), nullptr, PHI(p), w[p], s, false);
@@ -860,6 +874,7 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
                 d.lam[a] = (int)Q->tab_lam[a];
                 d.radices[a] = Q->ax[a].radices;
             }
+            d.Tmap = T_ != nullptr ? T_[p] : nullptr;
             d.cp = ctrl_params(const_cast<bfm_plan>(Q));
             d.cp.nqt = (int)dct_multi_inv_parts(d.n0);
             d.cp.nqs = ct_multi_col_groups(d.n0, d.n1);
@@ -868,6 +883,7 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
             memcpy(img.data() + sizeof(BatchHead) + (size_t)k * sizeof(PairDev), &d, sizeof(d));
             c.n0.push_back(d.n0);
             c.n1.push_back(d.n1);
+            c.n0map.push_back(d.Tmap != nullptr ? d.n0 : 0);
         }
         chunks.push_back(c);
         images.push_back(std::move(img));
@@ -885,14 +901,17 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
         for (const BatchHead &x : h) *out = *out && x.all_done != 0;
         return BFM_OK;
     };
+    for (MultiChunk &c : chunks) {   // finishing passes: no pair above its slot count of workgroups
+        long long epb = 4 * kRedBlock;
+        for (int k = 0; k < c.np; ++k) {
+            const long long N = (long long)c.n0[k] * c.n1[k];
+            while ((N + epb - 1) / epb > w[c.first + k].slot_len) epb += 4 * kRedBlock;
+        }
+        c.epb = epb;
+    }
     const int maxit = P[0]->prm.max_iters;
     int it = 0;
     bool done = false;
-    if (maxit > 0) {   // the first iteration per pair: its heads compute <p, tgt> directly
-        for (int p = 0; p < np; ++p)
-            HIP_TRY(enqueue_iterations<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), 0, 1, s));
-        it = 1;
-    }
     if (maxit - it >= K) {
         hipStream_t cap = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -922,9 +941,11 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
         HIP_TRY(multi_iterations<T>(chunks, maxit - it, s));
         it = maxit;
     }
-    for (int p = 0; p < np; ++p) {
-        HIP_TRY(enqueue_final_head<T>(P[p], w[p], MU(p), NU(p), PHI(p), PSI(p), it, s));
-        HIP_TRY(enqueue_finish<T>(P[p], w[p], MU(p), PHI(p), PSI(p), T_ != nullptr ? (T *)T_[p] : nullptr, s));
+    // the last head (no-op for stopped pairs), then the outputs
+    for (const MultiChunk &c : chunks) {
+        HIP_TRY(multi_head<T>(c, 0, s));
+        HIP_TRY(launch_map_multi<T>(c.tab, c.n0map.data(), c.n1.data(), c.np, s));
+        HIP_TRY(launch_finish_multi<T>(c.tab, c.n0.data(), c.n1.data(), c.np, c.epb, s));
     }
     for (int p = 0; p < np; ++p)
         HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));

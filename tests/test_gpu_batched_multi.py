@@ -60,8 +60,10 @@ def _compare(rb, mus, nus, iters, dtype, **kw):
         if dtype == torch.float64:
             assert float(cells.max()) <= 1e-8, i
         else:
+            # a few float32 ulps of phi^c (~1e-7) times n / 2 from the central
+            # difference, in cells of n: ~5e-8 n^2, 0.05 cells at n = 1024
             assert float(cells.max()) <= 0.5, i
-            assert float(torch.quantile(cells.float(), 0.99)) <= 1e-2, i
+            assert float(torch.quantile(cells.float(), 0.99)) <= 0.05, i
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
