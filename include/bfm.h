@@ -135,6 +135,22 @@ bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, const void *
                      void *phi, void *psi, void *T, void *workspace, size_t ws_bytes,
                      void *stream, bfm_result *result);
 
+/* bfm_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, outputs, validation and
+ * synchronisation as bfm_solve; the solve's scratch lives in a static device
+ * array of 64 MiB (67108864 bytes) that the library holds on every GPU it runs
+ * on until the process ends.  Plans whose bfm_plan_workspace_bytes exceeds
+ * that size are rejected with BFM_EWORKSPACE before any device call (float32
+ * 2048^2 and float64 1536^2 fit; float32 4096^2 does not).  The device is the
+ * calling thread's current device, which must be the device of `stream`.
+ * Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (from several threads or streams) race and must be serialised by the
+ * caller.  Each call re-initialises everything it reads from the array, so
+ * nothing carries over from an earlier call. */
+bfm_status bfm_solve_noalloc(bfm_plan plan, const void *mu, const void *nu, const void *phi_init,
+                             void *phi, void *psi, void *T, void *stream, bfm_result *result);
+
 /* Batched solve of `npairs` independent problems (Algorithm 1 for each),
  * advanced together: after the first iteration, iters_per_graph iterations of
  * every problem are captured once into a HIP graph (independent problems on

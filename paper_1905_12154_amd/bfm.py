@@ -25,7 +25,7 @@ EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
             "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass", "bfm_interpolate",
-            "bfm_grad_batched"]
+            "bfm_solve_noalloc", "bfm_grad_batched"]
 
 
 class BFMError(RuntimeError):
@@ -75,6 +75,7 @@ def lib():
         L.bfm_plan_destroy.restype = None
         L.bfm_plan_workspace_bytes.argtypes = [vp, P(sz)]
         L.bfm_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, P(Result)]
+        L.bfm_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, P(Result)]
         L.bfm_ctransform.argtypes = [vp, vp, vp, vp, sz, vp]
         L.bfm_pushforward.argtypes = [vp, vp, vp, vp, vp, P(dbl), vp, sz, vp]
         L.bfm_poisson_neumann.argtypes = [vp, vp, vp, P(dbl), vp, sz, vp]

@@ -612,6 +612,55 @@ extern "C" bfm_status bfm_solve(bfm_plan plan, const void *mu, const void *nu, c
                              (float *)psi, (float *)T, w, s, result);
 }
 
+// ------------------------------------------------- allocation-free solve
+
+// bfm_solve_noalloc keeps the workspace of a solve in this file-scope device
+// array (one copy on every GPU the library runs on, held until the process
+// ends) for callers that cannot allocate device memory.  In host code
+// `scratch` names a host-side stand-in, not device memory: its device
+// address is looked up once per device with hipGetSymbolAddress and only that
+// address is handed to kernels and copies.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the calling thread's current device.
+static bfm_status scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BFM_EDEVICE, "device id %d is outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev] == nullptr) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (p == nullptr || ((uintptr_t)p & 255) != 0)
+            return fail(BFM_EDEVICE, "static scratch of device %d has no usable address", dev);
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_solve_noalloc(bfm_plan plan, const void *mu, const void *nu, const void *phi_init,
+                                        void *phi, void *psi, void *T, void *stream, bfm_result *result)
+{
+    if (plan == nullptr) return fail(BFM_EINVAL, "plan is NULL");
+    if (plan->total > kNoAllocScratchBytes)
+        return fail(BFM_EWORKSPACE,
+                    "bfm_solve_noalloc: this plan needs %zu bytes of scratch, more than the %zu bytes of the "
+                    "static array; use bfm_solve with a caller workspace",
+                    plan->total, kNoAllocScratchBytes);
+    void *ws = nullptr;
+    bfm_status st = scratch_address(&ws);
+    if (st != BFM_OK) return st;
+    return bfm_solve(plan, mu, nu, phi_init, phi, psi, T, ws, kNoAllocScratchBytes, stream, result);
+}
+
 // ------------------------------------------------------------- batched
 
 // Many independent problems (each with its own plan, workspace and device

@@ -142,6 +142,25 @@ def test_header_is_plain_c():
     assert r.returncode == 0, r.stderr
 
 
+def test_noalloc_rejects_plans_above_its_static_scratch():
+    """bfm_solve_noalloc refuses a plan whose workspace exceeds its 64 MiB
+    static array before any device call; plans that fit are not refused by
+    that check (float32 2048^2 and float64 1536^2 fit, float32 4096^2 does
+    not)."""
+    L = bfm.lib()
+    res = bfm.Result()
+    d = [ctypes.c_void_p(0x1000 + 0x100 * k) for k in range(5)]
+    for shape, dt, fits in (((4096, 4096), "float32", False), ((2048, 2048), "float64", False),
+                            ((2048, 2048), "float32", True), ((1536, 1536), "float64", True)):
+        plan = bfm.Plan(shape, dtype=dt)
+        assert (plan.ws_bytes <= 64 << 20) == fits
+        if not fits:
+            st = L.bfm_solve_noalloc(plan.handle, d[0], d[1], None, d[2], d[3], None, None, ctypes.byref(res))
+            assert st == bfm.BFM_EWORKSPACE
+            assert "static array" in L.bfm_last_error().decode()
+    assert L.bfm_solve_noalloc(None, d[0], d[1], None, d[2], d[3], None, None, ctypes.byref(res)) == bfm.BFM_EINVAL
+
+
 def test_grad_batched_validation_before_any_launch():
     L = bfm.lib()
     plan = bfm.Plan((32, 32), dtype="float64")
