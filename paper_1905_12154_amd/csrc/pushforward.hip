@@ -26,7 +26,8 @@
 // covering all its targets (LDS atomics) and then adds each non-zero box
 // cell to the global density once.  Tiles whose targets spread over more
 // than the LDS box holds deposit with global atomics directly (no
-// contention there).
+// contention there).  float32 boxes hold unsigned fixed-point sums (LDS
+// integer atomics; see BoxCell), float64 boxes float64 sums.
 #include <climits>
 
 #include "common.hpp"
@@ -40,6 +41,17 @@ namespace bfm {
 // boxes overflow to global atomics more often and were slower; in 3D a
 // larger box was slower.
 template <typename T, int D> constexpr int box_cap() { return (D == 3 ? 16384 : 32768) / (int)sizeof(T); }
+
+// Box cells: float32 deposits accumulate in unsigned 32-bit fixed point (an
+// LDS integer atomic add is about 40 times cheaper on gfx950 than a float
+// one), float64 deposits in float64.  Per tile the fixed-point unit is
+// tile_mass / kFixOne, so no cell can exceed 2^32 even if all of the tile's
+// mass lands in it; each deposit is rounded to that unit once (as precise as
+// the float32 product it comes from), the integer sums are exact, and each
+// flushed cell is converted back with one float32 product.
+template <typename T> struct BoxCell { using type = T; };
+template <> struct BoxCell<float> { using type = unsigned; };
+constexpr float kFixOne = 4.29e9f;   // below 2^32 by more than the rounding of the deposits
 
 template <int D> struct Tile;
 // 2D: 16 x 32 tiles (two cells per lane) spread the tiles with mass of a
@@ -105,9 +117,10 @@ template <typename T> __device__ __forceinline__ T tpow(T x, T y) {
 // alternating bound sets, `kused` counts the tiles with mass processed so far.
 template <typename T, int D, bool GEN>
 __device__ __forceinline__ void
-splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)[D], long long tile,
+splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)[D], const T (&hn)[D], long long tile,
            const T *__restrict__ pc, const T *__restrict__ src, T *__restrict__ rho, T *__restrict__ Tout, T tmix,
-           T *box, int (*bnd)[2 * D], int &kused, double &accP, double &accJ)
+           typename BoxCell<T>::type *box, int (*bnd)[2 * D], float (*tmw)[kRedBlock / kWave], int &kused,
+           double &accP, double &accJ)
 {
     constexpr int PER = Tile<D>::cells / kRedBlock;   // cells per lane
     constexpr int kBoxCap = box_cap<T, D>();
@@ -200,8 +213,8 @@ splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)
                     d = (p0 - pm) * fn;
                 else
                     d = (pp - pm) * (T(0.5) * fn);
-                const T x = (T(i) + T(0.5)) / fn;
-                const T lo_t = T(0.5) / fn;
+                const T x = (T(i) + T(0.5)) * hn[a];   // cell centre (i + 1/2) h
+                const T lo_t = T(0.5) * hn[a];
                 if constexpr (GEN) {
                     if (pw[a] != T(2)) d = copysign(tpow(fabs(d), ex[a]), d);
                 }
@@ -231,6 +244,22 @@ splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)
             } else {
                 s[q] = T(0);
             }
+        }
+        // the tile's deposited mass (float32 fixed-point unit): per wave by
+        // DPP row rotations and the four row sums, one LDS slot per wave
+        if constexpr (sizeof(T) == 4) {
+            float m = 0.f;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) m += s[q];
+            m += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(m), __float_as_int(m), 0x121, 0xf, 0xf, false));
+            m += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(m), __float_as_int(m), 0x122, 0xf, 0xf, false));
+            m += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(m), __float_as_int(m), 0x124, 0xf, 0xf, false));
+            m += __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(m), __float_as_int(m), 0x128, 0xf, 0xf, false));
+            const float wm = (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 0)) +
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 16))) +
+                             (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 32)) +
+                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 48)));
+            if ((threadIdx.x & (kWave - 1)) == 0) tmw[kused & 1][threadIdx.x / kWave] = wm;
         }
         // box bounds: reduce across the wave first, one LDS atomic per wave
 #pragma unroll
@@ -265,7 +294,23 @@ splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)
             bs[a] = bb[D + a] - bb[a] + 1;
             area *= bs[a];
         }
-        if (area <= kBoxCap) {
+        // floor(r / bs) = umulhi(r, floor(2^32 / bs) + 1) whenever r * bs < 2^32
+        // (here r < area <= 8192 and bs <= area); bs >= 2, since a box spans at
+        // least two cells per axis, keeps the reciprocal within 32 bits
+        unsigned bdiv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) bdiv[a] = 0xffffffffu / (unsigned)bs[a] + 1u;
+        float fix_scale = 0.f, fix_unit = 0.f;
+        bool fits = area <= kBoxCap;
+        if constexpr (sizeof(T) == 4) {
+            float tm = 0.f;
+#pragma unroll
+            for (int w = 0; w < kRedBlock / kWave; ++w) tm += tmw[kused & 1][w];
+            fits = fits && tm > 1e-30f;   // a unit too small for float32 goes to the global path
+            fix_scale = kFixOne / tm;
+            fix_unit = tm / kFixOne;
+        }
+        if (fits) {
             // the box is all zero here: cleared at the start and by every flush;
             // all lanes take part in each deposit (lanes without mass pass a
             // key of their own that is negative)
@@ -281,20 +326,34 @@ splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)
                         w *= bit ? wup[q][a] : T(1) - wup[q][a];
                         off = off * bs[a] + (lo[q][a] + bit - bl[a]);
                     }
-                    box_deposit(box, s[q] != T(0) ? off : -1 - (int)(threadIdx.x & (kWave - 1)), w);
+                    if constexpr (sizeof(T) == 4) {
+                        if (s[q] != T(0)) atomicAdd(&box[off], (unsigned)(w * fix_scale + 0.5f));
+                    } else {
+                        box_deposit(box, s[q] != T(0) ? off : -1 - (int)(threadIdx.x & (kWave - 1)), w);
+                    }
                 }
             }
             __syncthreads();
             for (int e = threadIdx.x; e < area; e += kRedBlock) {
-                const T v = box[e];
-                box[e] = T(0);
+                T v;
+                if constexpr (sizeof(T) == 4) {
+                    const unsigned qv = box[e];
+                    box[e] = 0u;
+                    v = qv != 0u ? (float)qv * fix_unit : 0.f;
+                } else {
+                    v = box[e];
+                    box[e] = T(0);
+                }
                 if (v != T(0)) {
-                    int r = e;
+                    // box cell e -> grid index; division by the box sizes as a
+                    // high product with a per-tile reciprocal
+                    unsigned r = (unsigned)e;
                     long long gi = 0;
 #pragma unroll
                     for (int a = D - 1; a >= 0; --a) {
-                        gi += (long long)(bl[a] + r % bs[a]) * g.stride[a];
-                        r /= bs[a];
+                        const unsigned qd = __umulhi(r, bdiv[a]);
+                        gi += (long long)(bl[a] + (int)(r - qd * (unsigned)bs[a])) * g.stride[a];
+                        r = qd;
                     }
                     atomicAdd(rho + gi, v);
                 }
@@ -323,20 +382,32 @@ splat_tile(const Grid &g, const int (&ntile)[D], const T (&pw)[D], const T (&ex)
 }
 
 template <typename T, int D>
-__device__ __forceinline__ void splat_setup(const Grid &g, int (&ntile)[D], T (&pw)[D], T (&ex)[D])
+__device__ __forceinline__ void splat_setup(const Grid &g, int (&ntile)[D], T (&pw)[D], T (&ex)[D], T (&hn)[D])
 {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         ntile[a] = (g.n[a] + Tile<D>::s[a] - 1) / Tile<D>::s[a];
         pw[a] = T(g.pw[a]);
         ex[a] = T(1.0 / (g.pw[a] - 1.0));
+        hn[a] = T(1) / T(g.n[a]);
     }
 }
 
-template <typename T, int D>
-__device__ __forceinline__ void splat_clear(T *box, int (*bnd)[2 * D])
+// First tile of workgroup b in the walk over a list of tiles with grid G:
+// workgroups are dispatched round-robin over the 8 XCDs, so with G a
+// multiple of 8 the XCD of b (b mod 8) takes a contiguous eighth of each
+// round of G tiles.  Neighbouring tiles share cache lines (a 3D tile row is
+// 32 bytes of a 128-byte line, and the deposits of neighbouring tiles
+// overlap), which then meet in one XCD's L2.  Tile k + G follows tile k.
+__device__ __forceinline__ long long splat_first_tile(long long b, long long G)
 {
-    for (int e = threadIdx.x; e < box_cap<T, D>(); e += kRedBlock) box[e] = T(0);
+    return (G & 7) == 0 ? (b & 7) * (G >> 3) + (b >> 3) : b;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void splat_clear(typename BoxCell<T>::type *box, int (*bnd)[2 * D])
+{
+    for (int e = threadIdx.x; e < box_cap<T, D>(); e += kRedBlock) box[e] = 0;
     if (threadIdx.x < 2 * D) {
         bnd[threadIdx.x / D][threadIdx.x % D] = 0x7fffffff;
         bnd[threadIdx.x / D][D + threadIdx.x % D] = -1;
@@ -353,18 +424,20 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
 {
     if (done != nullptr && *done) return;
     __shared__ double sh[kRedBlock / kWave];
-    __shared__ T box[box_cap<T, D>()];
+    __shared__ typename BoxCell<T>::type box[box_cap<T, D>()];
     __shared__ int bnd[2][2 * D];   // box bounds, alternating between consecutive tiles with mass
+    __shared__ float tmw[2][kRedBlock / kWave];   // per-wave tile mass, same alternation
     int ntile[D];
-    T pw[D], ex[D];   // exponent p_a of the cost and 1 / (p_a - 1)
-    splat_setup<T, D>(g, ntile, pw, ex);
+    T pw[D], ex[D], hn[D];   // exponent p_a of the cost, 1 / (p_a - 1), 1 / n_a
+    splat_setup<T, D>(g, ntile, pw, ex, hn);
     double accP = 0.0, accJ = 0.0;
     splat_clear<T, D>(box, bnd);
     int kused = 0;   // tiles with mass processed so far by this workgroup
     const long long count = tiles != nullptr ? (long long)tiles[0] : ntiles_total;
-    for (long long k = blockIdx.x; k < count; k += gridDim.x) {
+    for (long long k = splat_first_tile(blockIdx.x, gridDim.x); k < count; k += gridDim.x) {
         const long long tile = tiles != nullptr ? (long long)tiles[1 + k] : k;
-        splat_tile<T, D, GEN>(g, ntile, pw, ex, tile, pc, src, rho, Tout, tmix, box, bnd, kused, accP, accJ);
+        splat_tile<T, D, GEN>(g, ntile, pw, ex, hn, tile, pc, src, rho, Tout, tmix, box, bnd, tmw, kused, accP,
+                              accJ);
     }
     const double P = block_reduce<R_SUM>(accP, sh);
     const double J = block_reduce<R_SUM>(accJ, sh);
@@ -380,15 +453,17 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
 // entries start at ent_mu / ent_nu), kBatchSplatGrid workgroups striding
 // over it.  A workgroup keeps its sums per pair and writes them when its walk
 // leaves the pair, at index (first entry it visited - the pair's first
-// entry): the pair's partials are then indices 0 .. min(grid, entries) - 1.
+// entry): every workgroup walks one residue class modulo the grid, so the
+// pair's partials are indices 0 .. min(grid, entries) - 1, one each.
 template <typename T>
 __global__ void __launch_bounds__(kRedBlock)
 splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
 {
     constexpr int D = 2;
     __shared__ double sh[kRedBlock / kWave];
-    __shared__ T box[box_cap<T, D>()];
+    __shared__ typename BoxCell<T>::type box[box_cap<T, D>()];
     __shared__ int bnd[2][2 * D];
+    __shared__ float tmw[2][kRedBlock / kWave];
     const PairDev *pairs = reinterpret_cast<const PairDev *>(tab + 1);
     const int np = tab->np;
     const int total = role ? tab->ent_total_nu : tab->ent_total_mu;
@@ -398,7 +473,7 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
     long long first = 0;
     Grid g{};
     int ntile[D];
-    T pw[D], ex[D];
+    T pw[D], ex[D], hn[D];
     const T *pc = nullptr, *src = nullptr;
     T *rho = nullptr;
     const int *tiles = nullptr;
@@ -414,7 +489,7 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
         }
         accP = accJ = 0.0;
     };
-    for (long long k = blockIdx.x; k < total; k += gridDim.x) {
+    for (long long k = splat_first_tile(blockIdx.x, gridDim.x); k < total; k += gridDim.x) {
         int p = cur < 0 ? 0 : cur;
         while (p + 1 < np && (role ? pairs[p + 1].ent_nu : pairs[p + 1].ent_mu) <= k) ++p;
         if (p != cur) {
@@ -433,7 +508,7 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
             g.N = (long long)Q.n0 * Q.n1;
             g.vol = 1.0 / (double)g.N;
             g.pw[0] = g.pw[1] = g.pw[2] = 2.0;
-            splat_setup<T, D>(g, ntile, pw, ex);
+            splat_setup<T, D>(g, ntile, pw, ex, hn);
             pc = (const T *)Q.pc;
             src = (const T *)(role ? Q.nu : Q.mu);
             rho = (T *)Q.rho;
@@ -441,7 +516,8 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
         }
         if (skip) continue;   // uniform: the pair has stopped
         const long long tile = tiles[1 + (k - (role ? pairs[p].ent_nu : pairs[p].ent_mu))];
-        splat_tile<T, D, false>(g, ntile, pw, ex, tile, pc, src, rho, nullptr, T(1), box, bnd, kused, accP, accJ);
+        splat_tile<T, D, false>(g, ntile, pw, ex, hn, tile, pc, src, rho, nullptr, T(1), box, bnd, tmw, kused,
+                                accP, accJ);
     }
     if (cur >= 0) flush();
 }
@@ -483,8 +559,9 @@ __global__ void __launch_bounds__(kRedBlock) map_multi_kernel(const BatchHead *_
                 d = (p0 - pm) * fn;
             else
                 d = (pp - pm) * (T(0.5) * fn);
-            const T x = (T(i) + T(0.5)) / fn;
-            const T lo_t = T(0.5) / fn;
+            const T hn = T(1) / fn;   // as the deposition: (i + 1/2) h with h = 1 / n
+            const T x = (T(i) + T(0.5)) * hn;
+            const T lo_t = T(0.5) * hn;
             Tout[(long long)a * N + id] = fmin(fmax(x - d, lo_t), T(1) - lo_t);
         }
     }
