@@ -75,7 +75,8 @@ def parse():
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 64-pair leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 3D 384^3 leg")
     ap.add_argument("--c5-iters", type=int, default=400)
-    ap.add_argument("--c5-tol", type=float, default=1e-5)
+    ap.add_argument("--c5-tol", type=float, default=3e-4,
+                    help="common stop gap of the batched leg (the smallest at which all 64 pairs converge)")
     ap.add_argument("--c4-iters", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-interp", action="store_true", help="skip the 1024^2 displacement-interpolation leg")

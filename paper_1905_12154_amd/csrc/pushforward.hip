@@ -59,44 +59,12 @@ template <int D> struct Tile;
 template <> struct Tile<2> { static constexpr int s[2] = {16, 32}; static constexpr int cells = 512; };
 template <> struct Tile<3> { static constexpr int s[3] = {8, 8, 8}; static constexpr int cells = 512; };
 
-// One deposit per lane into the LDS box (key = box cell, or < 0 for none;
-// every lane of the wave calls this).  Where the map compresses mass,
-// neighbouring lanes hit the same cell and LDS atomics on one address
-// serialise.  For float32, runs of equal cells inside each row of 16 lanes
-// are first summed with DPP row shifts (a segmented inclusive scan: each
-// lane finds the head of its run by a max-scan, then adds partial sums from
-// lanes of the same run), and only the last lane of each run adds to LDS.
-template <int CTRL>
-__device__ __forceinline__ int dpp_row(int old, int v) {
-    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
-}
-
+// One float64 deposit per lane into the LDS box (key = box cell, or < 0 for
+// none).
 template <typename T>
 __device__ __forceinline__ void box_deposit(T *box, int key, T w)
 {
-    if constexpr (sizeof(T) == 4) {
-        constexpr int SHR1 = 0x111, SHR2 = 0x112, SHR4 = 0x114, SHR8 = 0x118, SHL1 = 0x101;
-        const int lane = threadIdx.x & 15;
-        const int kprev = dpp_row<SHR1>(INT_MIN, key);   // INT_MIN at the start of a row
-        const int knext = dpp_row<SHL1>(INT_MIN, key);   // INT_MIN at the end of a row
-        int h = kprev != key ? lane : -1;                // this lane starts a run
-        h = max(h, dpp_row<SHR1>(-1, h));
-        h = max(h, dpp_row<SHR2>(-1, h));
-        h = max(h, dpp_row<SHR4>(-1, h));
-        h = max(h, dpp_row<SHR8>(-1, h));                // head of this lane's run
-        float v = w;
-        float t = __int_as_float(dpp_row<SHR1>(0, __float_as_int(v)));
-        if (lane - 1 >= h) v += t;
-        t = __int_as_float(dpp_row<SHR2>(0, __float_as_int(v)));
-        if (lane - 2 >= h) v += t;
-        t = __int_as_float(dpp_row<SHR4>(0, __float_as_int(v)));
-        if (lane - 4 >= h) v += t;
-        t = __int_as_float(dpp_row<SHR8>(0, __float_as_int(v)));
-        if (lane - 8 >= h) v += t;
-        if (knext != key && key >= 0) atomicAdd(&box[key], (T)v);
-    } else {
-        if (key >= 0) atomicAdd(&box[key], w);
-    }
+    if (key >= 0) atomicAdd(&box[key], w);
 }
 
 // Persistent workgroups walk the tiles in a grid-stride loop; a tile without
