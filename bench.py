@@ -186,6 +186,10 @@ def batched_leg(iters, tol):
     tb = time.perf_counter() - t0
     gm = [m.clone().requires_grad_(True) for m in mus]
     gn = [v.clone().requires_grad_(True) for v in nus]
+    # warm-up of the autograd path (first backward: autograd engine, kernel loads)
+    bfm.w2_loss_batched(gm, gn, max_iters=1, tol=tol).sum().backward()
+    for t in gm + gn:
+        t.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     vals = bfm.w2_loss_batched(gm, gn, max_iters=iters, tol=tol)

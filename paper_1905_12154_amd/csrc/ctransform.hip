@@ -776,16 +776,24 @@ hipError_t ctransform_field(const Grid &g, const T *in, T *out, const int32_t *d
 // ------------------------------------------------------------ multi-pair
 // One pass of the 2D transform for every pair of a batch in one launch
 // (rows: u = -p into F; columns: F into p^c or q, the latter with the fused
-// sum of q * src).  Workgroups of 256 lanes, C = 16 points per lane, tpl
-// lanes per line (the next power of two >= n / 16) and 256 / tpl lines per
-// workgroup, so every pair's lines fill whole workgroups whatever its size.
+// sum of q * src).  Workgroups of 256 lanes, C points per lane (16 for lines
+// longer than 256 points, 4 for shorter ones, whose workgroups would
+// otherwise be few and long: a small pair's pass is a chain of dependent LDS
+// steps whose length grows with C), tpl lanes per line (the next power of two
+// >= n / C) and 256 / tpl lines per workgroup, so every pair's lines fill
+// whole workgroups whatever its size.
 constexpr int kMultiCtThreads = 256;
-constexpr int kMultiCtC = 16;
+constexpr int kMultiCtC = 16;        // lines longer than kMultiCtShort points
+constexpr int kMultiCtCShort = 4;    // lines of at most kMultiCtShort points
+constexpr int kMultiCtShort = 256;
+
+__host__ __device__ inline int multi_c(int n) { return n <= kMultiCtShort ? kMultiCtCShort : kMultiCtC; }
 
 __host__ __device__ inline int multi_tpl(int n)
 {
+    const int C = multi_c(n);
     int tpl = 1;
-    while (tpl * kMultiCtC < n) tpl <<= 1;
+    while (tpl * C < n) tpl <<= 1;
     return tpl;
 }
 
@@ -814,19 +822,11 @@ __device__ __forceinline__ int batch_pair(const BatchIdx &bi)
 }
 
 // which: 0 head rows, 1 head columns, 2 step rows, 3 step columns (+ sum)
-template <typename T, bool STRIDED>
-__global__ void __launch_bounds__(kMultiCtThreads)
-ct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role, int which)
+template <typename T, bool STRIDED, int C>
+__device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &bi, int pr, int role, int which,
+                                              unsigned char *smem, int *wave_tot, double *dred)
 {
-    constexpr int C = kMultiCtC;
     using V4 = typename vec4<T>::type;
-    const int pr = batch_pair(bi);
-    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[pr];
-    if (P.st->done) return;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int wave_tot[16];
-    __shared__ double dred[kMultiCtThreads / kWave];
-
     const T *pfield = (const T *)(role ? P.psi : P.phi);
     const T *src = (const T *)(role ? P.nu : P.mu);
     const T *in = STRIDED ? (const T *)P.F : pfield;
@@ -961,6 +961,22 @@ ct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role, int wh
             P.part[S_Q_SRC * P.slot_len + (blockIdx.x - bi.off[pr])] = sum;
         }
     }
+}
+
+template <typename T, bool STRIDED>
+__global__ void __launch_bounds__(kMultiCtThreads)
+ct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role, int which)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wave_tot[16];
+    __shared__ double dred[kMultiCtThreads / kWave];
+    const int pr = batch_pair(bi);
+    const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[pr];
+    if (P.st->done) return;
+    if (multi_c(STRIDED ? P.n0 : P.n1) == kMultiCtCShort)
+        ct_multi_body<T, STRIDED, kMultiCtCShort>(P, bi, pr, role, which, smem, wave_tot, dred);
+    else
+        ct_multi_body<T, STRIDED, kMultiCtC>(P, bi, pr, role, which, smem, wave_tot, dred);
 }
 
 template <typename T>

@@ -165,7 +165,7 @@ hipError_t launch_ctrl(DevState *st, const double *partials, const double *gpart
 // pair (BatchIdx), so a workgroup finds its pair by a binary search over
 // kernel arguments.
 constexpr int kBatchChunk = 64;
-constexpr int kBatchSplatGrid = 2048;   // workgroups of the joint deposition
+constexpr int kBatchSplatGrid = 2048;   // most workgroups of the joint deposition
 
 struct PairDev {
     const void *mu, *nu;
@@ -190,7 +190,11 @@ struct BatchHead {
     int np;
     int ent_total_mu, ent_total_nu;   // lengths of the joint deposition lists (device-filled)
     int all_done;                     // 1 when every pair's stop flag is set (launch_batch_done)
+    int splat_grid;                   // workgroups of the joint deposition launch (host-set)
+    int nactive;                      // pairs whose stop flag is clear (launch_batch_done)
+    unsigned long long done_mask;     // bit p: pair p has stopped (launch_batch_done)
 };
+static_assert(sizeof(BatchHead) % 8 == 0, "the pair table after the head stays 8-byte aligned");
 constexpr size_t kBatchTableBytes = sizeof(BatchHead) + kBatchChunk * sizeof(PairDev);
 
 struct BatchIdx {
@@ -205,7 +209,7 @@ template <typename T>
 hipError_t launch_ct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int which,
                            hipStream_t stream);
 template <typename T>
-hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, hipStream_t stream);
+hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, int grid, hipStream_t stream);
 hipError_t launch_batch_entries(BatchHead *tab, hipStream_t stream);
 // modes of launch_dct_multi (the DCT pass kinds of dct.hip)
 constexpr int kDctFwd = 0, kDctInv = 1, kDctFused = 2;

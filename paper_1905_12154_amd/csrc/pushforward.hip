@@ -418,8 +418,8 @@ splat_kernel(Grid g, long long ntiles_total, const T *__restrict__ pc, const T *
 // ------------------------------------------------------------ multi-pair
 // The deposition of every pair of a batch (2D, quadratic cost) in one launch:
 // the pairs' lists of tiles with mass are walked as one joint list (pair p's
-// entries start at ent_mu / ent_nu), kBatchSplatGrid workgroups striding
-// over it.  A workgroup keeps its sums per pair and writes them when its walk
+// entries start at ent_mu / ent_nu), splat_grid workgroups (at most
+// kBatchSplatGrid, at most the pairs' tile count) striding over it.  A workgroup keeps its sums per pair and writes them when its walk
 // leaves the pair, at index (first entry it visited - the pair's first
 // entry): every workgroup walks one residue class modulo the grid, so the
 // pair's partials are indices 0 .. min(grid, entries) - 1, one each.
@@ -572,10 +572,10 @@ hipError_t launch_batch_entries(BatchHead *tab, hipStream_t stream)
 }
 
 template <typename T>
-hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, hipStream_t stream)
+hipError_t launch_splat_multi(const BatchHead *tab, int np, int role, int grid, hipStream_t stream)
 {
-    if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((splat_multi_kernel<T>), dim3(kBatchSplatGrid), dim3(kRedBlock), 0, stream, tab, role);
+    if (np < 1 || np > kBatchChunk || grid < 1 || grid > kBatchSplatGrid) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((splat_multi_kernel<T>), dim3(grid), dim3(kRedBlock), 0, stream, tab, role);
     return hipGetLastError();
 }
 
@@ -710,10 +710,10 @@ template hipError_t launch_splat<float>(const Grid &, const float *, const float
 template hipError_t launch_splat<double>(const Grid &, const double *, const double *, double *, double *,
                                          double *, double *, int, const int32_t *, hipStream_t, double, const int *);
 template hipError_t launch_tile_list<float>(const Grid &, const float *, int *, int *, hipStream_t);
-template hipError_t launch_splat_multi<float>(const BatchHead *, int, int, hipStream_t);
+template hipError_t launch_splat_multi<float>(const BatchHead *, int, int, int, hipStream_t);
 template hipError_t launch_map_multi<float>(const BatchHead *, const int *, const int *, int, hipStream_t);
 template hipError_t launch_map_multi<double>(const BatchHead *, const int *, const int *, int, hipStream_t);
-template hipError_t launch_splat_multi<double>(const BatchHead *, int, int, hipStream_t);
+template hipError_t launch_splat_multi<double>(const BatchHead *, int, int, int, hipStream_t);
 template hipError_t launch_tile_list<double>(const Grid &, const double *, int *, int *, hipStream_t);
 
 }  // namespace bfm

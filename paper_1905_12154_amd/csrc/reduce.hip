@@ -372,17 +372,26 @@ ctrl_multi_kernel(const BatchHead *__restrict__ tab, int role, int mode)
     const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[blockIdx.x];
     CtrlParams prm = P.cp;
     const int ent = (role ? P.tiles_nu : P.tiles_mu)[0];
-    prm.nsplat = ent < kBatchSplatGrid ? ent : kBatchSplatGrid;
+    prm.nsplat = ent < tab->splat_grid ? ent : tab->splat_grid;
     ctrl_body(P.st, P.part, P.gpart, mode, prm, P.trace);
 }
 
-__global__ void batch_done_kernel(BatchHead *tab)
+// One wave, lane p for pair p (np <= kBatchChunk = 64): the stop flags as a
+// bit mask, their count and whether all are set.
+__global__ void __launch_bounds__(kWave) batch_done_kernel(BatchHead *tab)
 {
+    static_assert(kBatchChunk <= kWave, "one lane per pair");
     const PairDev *pairs = reinterpret_cast<const PairDev *>(tab + 1);
-    int all = 1;
-    for (int p = threadIdx.x; p < tab->np; p += blockDim.x) all &= pairs[p].st->done != 0;
-    all = __syncthreads_and(all);
-    if (threadIdx.x == 0) tab->all_done = all;
+    const int np = tab->np;
+    const int p = threadIdx.x;
+    const bool stopped = p < np ? pairs[p].st->done != 0 : true;
+    const unsigned long long mask = __ballot(stopped);
+    if (p == 0) {
+        const unsigned long long live = np >= 64 ? ~0ull : ((1ull << np) - 1);
+        tab->done_mask = mask & live;
+        tab->nactive = np - __popcll(mask & live);
+        tab->all_done = (mask & live) == live;
+    }
 }
 
 hipError_t launch_batch_done(BatchHead *tab, hipStream_t stream)

@@ -811,11 +811,13 @@ static bool multi_applies(int np, const bfm_plan *P)
 
 namespace {
 struct MultiChunk {
-    int first = 0, np = 0;
-    BatchHead *tab = nullptr;     // device table in the workspace of pair `first`
+    BatchHead *tab = nullptr;     // device table in the workspace of the chunk's first pair
+    std::vector<int> pair;        // batch index of each entry
     std::vector<int> n0, n1;
     std::vector<int> n0map;       // n0 of the pairs with a map output, 0 for the others
+    int splat_grid = 0;           // workgroups of the joint deposition
     long long epb = 0;            // elements per workgroup of the finishing passes
+    std::vector<unsigned char> img;   // host image of the table
 };
 }  // namespace
 
@@ -826,12 +828,12 @@ struct MultiChunk {
 template <typename T>
 static hipError_t multi_head(const MultiChunk &c, int role, hipStream_t s)
 {
-    const int np = c.np;
+    const int np = (int)c.pair.size();
     const int head = role ? CTRL_HEAD_PSI : CTRL_HEAD_PHI;
     hipError_t e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 0, s)) != hipSuccess) return e;
     if ((e = launch_ct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, 1, s)) != hipSuccess) return e;
-    if ((e = launch_splat_multi<T>(c.tab, np, role, s)) != hipSuccess) return e;
+    if ((e = launch_splat_multi<T>(c.tab, np, role, c.splat_grid, s)) != hipSuccess) return e;
     if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFwd, s)) != hipSuccess) return e;
     if ((e = launch_dct_multi<T>(c.tab, c.n0.data(), c.n1.data(), np, role, kDctFused, s)) != hipSuccess) return e;
     return launch_ctrl_multi(c.tab, np, role, head | CTRL_REUSE_DOT, s);
@@ -840,7 +842,7 @@ static hipError_t multi_head(const MultiChunk &c, int role, hipStream_t s)
 template <typename T>
 static hipError_t multi_half_step(const MultiChunk &c, int role, hipStream_t s)
 {
-    const int np = c.np;
+    const int np = (int)c.pair.size();
     const int step = role ? CTRL_STEP_PSI : CTRL_STEP_PHI;
     hipError_t e;
     if ((e = multi_head<T>(c, role, s)) != hipSuccess) return e;
@@ -883,81 +885,100 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
         bfm_status st = check_inputs(hs[p]);
         if (st != BFM_OK) return fail(st, "pair %d: %s", p, g_last_error.c_str());
     }
-    // device tables, one per chunk of pairs
-    std::vector<MultiChunk> chunks;
-    std::vector<std::vector<unsigned char>> images;
-    for (int first = 0; first < np; first += kBatchChunk) {
-        MultiChunk c;
-        c.first = first;
-        c.np = np - first < kBatchChunk ? np - first : kBatchChunk;
-        c.tab = w[first].batch;
-        std::vector<unsigned char> img(sizeof(BatchHead) + (size_t)c.np * sizeof(PairDev), 0);
-        BatchHead hd{};
-        hd.np = c.np;
-        memcpy(img.data(), &hd, sizeof(hd));
-        for (int k = 0; k < c.np; ++k) {
-            const int p = first + k;
-            const bfm_plan_s *Q = P[p];
-            const Ws &W = w[p];
-            PairDev d{};
-            d.mu = mu_[p];
-            d.nu = nu_[p];
-            d.phi = phi_[p];
-            d.psi = psi_[p];
-            d.pc = W.pc;
-            d.rho = W.rho;
-            d.F = W.f;
-            d.st = W.st;
-            d.trace = W.trace;
-            d.part = W.part;
-            d.gpart = W.gpart;
-            d.tables = W.tables;
-            d.tiles_mu = W.tiles_mu;
-            d.tiles_nu = W.tiles_nu;
-            d.slot_len = W.slot_len;
-            d.n0 = Q->g.n[0];
-            d.n1 = Q->g.n[1];
-            for (int a = 0; a < 2; ++a) {
-                d.tw[a] = (int)Q->tab_tw[a];
-                d.qw[a] = (int)Q->tab_qw[a];
-                d.lam[a] = (int)Q->tab_lam[a];
-                d.radices[a] = Q->ax[a].radices;
+    // device tables, one per chunk of at most kBatchChunk pairs of `ids`
+    auto make_chunks = [&](const std::vector<int> &ids, std::vector<MultiChunk> &out) -> bfm_status {
+        out.clear();
+        for (size_t first = 0; first < ids.size(); first += kBatchChunk) {
+            MultiChunk c;
+            const int cnp = (int)(ids.size() - first < (size_t)kBatchChunk ? ids.size() - first : kBatchChunk);
+            c.tab = w[ids[first]].batch;
+            c.img.assign(sizeof(BatchHead) + (size_t)cnp * sizeof(PairDev), 0);
+            long long tiles = 0;
+            for (int k = 0; k < cnp; ++k) {
+                const int p = ids[first + k];
+                const bfm_plan_s *Q = P[p];
+                const Ws &W = w[p];
+                PairDev d{};
+                d.mu = mu_[p];
+                d.nu = nu_[p];
+                d.phi = phi_[p];
+                d.psi = psi_[p];
+                d.pc = W.pc;
+                d.rho = W.rho;
+                d.F = W.f;
+                d.st = W.st;
+                d.trace = W.trace;
+                d.part = W.part;
+                d.gpart = W.gpart;
+                d.tables = W.tables;
+                d.tiles_mu = W.tiles_mu;
+                d.tiles_nu = W.tiles_nu;
+                d.slot_len = W.slot_len;
+                d.n0 = Q->g.n[0];
+                d.n1 = Q->g.n[1];
+                for (int a = 0; a < 2; ++a) {
+                    d.tw[a] = (int)Q->tab_tw[a];
+                    d.qw[a] = (int)Q->tab_qw[a];
+                    d.lam[a] = (int)Q->tab_lam[a];
+                    d.radices[a] = Q->ax[a].radices;
+                }
+                d.Tmap = T_ != nullptr ? T_[p] : nullptr;
+                d.cp = ctrl_params(const_cast<bfm_plan>(Q));
+                d.cp.nqt = (int)dct_multi_inv_parts(d.n0);
+                d.cp.nqs = ct_multi_col_groups(d.n0, d.n1);
+                if (d.cp.nqt > W.slot_len || d.cp.nqs > W.slot_len || (d.n1 + 3) / 4 != Q->gparts)
+                    return fail(BFM_EDEVICE, "pair %d: multi-pair partial counts exceed the workspace slots", p);
+                memcpy(c.img.data() + sizeof(BatchHead) + (size_t)k * sizeof(PairDev), &d, sizeof(d));
+                c.pair.push_back(p);
+                c.n0.push_back(d.n0);
+                c.n1.push_back(d.n1);
+                c.n0map.push_back(d.Tmap != nullptr ? d.n0 : 0);
+                tiles += splat_tile_count(Q->g);
             }
-            d.Tmap = T_ != nullptr ? T_[p] : nullptr;
-            d.cp = ctrl_params(const_cast<bfm_plan>(Q));
-            d.cp.nqt = (int)dct_multi_inv_parts(d.n0);
-            d.cp.nqs = ct_multi_col_groups(d.n0, d.n1);
-            if (d.cp.nqt > W.slot_len || d.cp.nqs > W.slot_len || (d.n1 + 3) / 4 != Q->gparts)
-                return fail(BFM_EDEVICE, "pair %d: multi-pair partial counts exceed the workspace slots", p);
-            memcpy(img.data() + sizeof(BatchHead) + (size_t)k * sizeof(PairDev), &d, sizeof(d));
-            c.n0.push_back(d.n0);
-            c.n1.push_back(d.n1);
-            c.n0map.push_back(d.Tmap != nullptr ? d.n0 : 0);
+            c.splat_grid = (int)(tiles < kBatchSplatGrid ? tiles : kBatchSplatGrid);
+            BatchHead hd{};
+            hd.np = cnp;
+            hd.splat_grid = c.splat_grid;
+            memcpy(c.img.data(), &hd, sizeof(hd));
+            out.push_back(std::move(c));
         }
-        chunks.push_back(c);
-        images.push_back(std::move(img));
-    }
-    for (size_t i = 0; i < chunks.size(); ++i) {
-        HIP_TRY(hipMemcpyAsync(chunks[i].tab, images[i].data(), images[i].size(), hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_batch_entries(chunks[i].tab, s));
-    }
-    auto all_done = [&](bool *out) -> bfm_status {
-        std::vector<BatchHead> h(chunks.size());
-        for (size_t i = 0; i < chunks.size(); ++i)
-            HIP_TRY(hipMemcpyAsync(&h[i], chunks[i].tab, sizeof(BatchHead), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        *out = true;
-        for (const BatchHead &x : h) *out = *out && x.all_done != 0;
         return BFM_OK;
     };
-    for (MultiChunk &c : chunks) {   // finishing passes: no pair above its slot count of workgroups
+    auto upload = [&](const std::vector<MultiChunk> &cs) -> bfm_status {
+        for (const MultiChunk &c : cs) {
+            HIP_TRY(hipMemcpyAsync(c.tab, c.img.data(), c.img.size(), hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_batch_entries(c.tab, s));
+        }
+        return BFM_OK;
+    };
+    auto heads = [&](const std::vector<MultiChunk> &cs, std::vector<BatchHead> &h) -> bfm_status {
+        h.resize(cs.size());
+        for (size_t i = 0; i < cs.size(); ++i)
+            HIP_TRY(hipMemcpyAsync(&h[i], cs[i].tab, sizeof(BatchHead), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return BFM_OK;
+    };
+    std::vector<int> ids(np);
+    for (int p = 0; p < np; ++p) ids[p] = p;
+    std::vector<MultiChunk> full;
+    bfm_status bst = make_chunks(ids, full);
+    if (bst != BFM_OK) return bst;
+    for (MultiChunk &c : full) {   // finishing passes: no pair above its slot count of workgroups
         long long epb = 4 * kRedBlock;
-        for (int k = 0; k < c.np; ++k) {
+        for (size_t k = 0; k < c.pair.size(); ++k) {
             const long long N = (long long)c.n0[k] * c.n1[k];
-            while ((N + epb - 1) / epb > w[c.first + k].slot_len) epb += 4 * kRedBlock;
+            while ((N + epb - 1) / epb > w[c.pair[k]].slot_len) epb += 4 * kRedBlock;
         }
         c.epb = epb;
     }
+    if ((bst = upload(full)) != BFM_OK) return bst;
+    // The iterations run on the chunks of the pairs still iterating: when at
+    // most half of the pairs of the current chunks are still running after a
+    // replay, the tables are rebuilt over those pairs alone and the graph is
+    // captured again, so stopped pairs stop costing workgroups and the
+    // deposition grid shrinks with the remaining tiles.
+    std::vector<MultiChunk> cur = full;
+    bool compacted = false;
     const int maxit = P[0]->prm.max_iters;
     int it = 0;
     bool done = false;
@@ -966,35 +987,67 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (ce == hipSuccess) {
-            ce = multi_iterations<T>(chunks, K, cap);
-            hipError_t ee = hipStreamEndCapture(cap, &graph);
-            if (ce == hipSuccess) ce = ee;
-        }
-        if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        bfm_status bst = BFM_OK;
+        auto drop_graph = [&]() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+        };
+        hipError_t ce = hipSuccess;
+        std::vector<BatchHead> h;
         while (ce == hipSuccess && bst == BFM_OK && maxit - it >= K) {
+            if (exec == nullptr) {
+                ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                if (ce == hipSuccess) {
+                    ce = multi_iterations<T>(cur, K, cap);
+                    hipError_t ee = hipStreamEndCapture(cap, &graph);
+                    if (ce == hipSuccess) ce = ee;
+                }
+                if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (ce != hipSuccess) break;
+            }
             ce = hipGraphLaunch(exec, s);
+            if (ce != hipSuccess) break;
             it += K;
-            if (ce == hipSuccess) bst = all_done(&done);
-            if (done) break;
+            if ((bst = heads(cur, h)) != BFM_OK) break;
+            int running = 0, size = 0;
+            for (size_t i = 0; i < cur.size(); ++i) {
+                running += h[i].nactive;
+                size += (int)cur[i].pair.size();
+            }
+            if (running == 0) {
+                done = true;
+                break;
+            }
+            if (2 * running <= size && maxit - it >= K) {
+                std::vector<int> live;
+                for (size_t i = 0; i < cur.size(); ++i)
+                    for (size_t k = 0; k < cur[i].pair.size(); ++k)
+                        if (!((h[i].done_mask >> k) & 1ull)) live.push_back(cur[i].pair[k]);
+                std::vector<MultiChunk> next;
+                if ((bst = make_chunks(live, next)) != BFM_OK) break;
+                if ((bst = upload(next)) != BFM_OK) break;
+                cur.swap(next);
+                compacted = true;
+                drop_graph();
+            }
         }
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        drop_graph();
         (void)hipStreamDestroy(cap);
         HIP_TRY(ce);
         if (bst != BFM_OK) return bst;
     }
     if (!done && it < maxit) {
-        HIP_TRY(multi_iterations<T>(chunks, maxit - it, s));
+        HIP_TRY(multi_iterations<T>(cur, maxit - it, s));
         it = maxit;
     }
-    // the last head (no-op for stopped pairs), then the outputs
-    for (const MultiChunk &c : chunks) {
+    // the last head (no-op for stopped pairs), then the outputs, on the full tables
+    if (compacted && (bst = upload(full)) != BFM_OK) return bst;
+    for (const MultiChunk &c : full) {
+        const int cnp = (int)c.pair.size();
         HIP_TRY(multi_head<T>(c, 0, s));
-        HIP_TRY(launch_map_multi<T>(c.tab, c.n0map.data(), c.n1.data(), c.np, s));
-        HIP_TRY(launch_finish_multi<T>(c.tab, c.n0.data(), c.n1.data(), c.np, c.epb, s));
+        HIP_TRY(launch_map_multi<T>(c.tab, c.n0map.data(), c.n1.data(), cnp, s));
+        HIP_TRY(launch_finish_multi<T>(c.tab, c.n0.data(), c.n1.data(), cnp, c.epb, s));
     }
     for (int p = 0; p < np; ++p)
         HIP_TRY(hipMemcpyAsync(&hs[p], w[p].st, sizeof(DevState), hipMemcpyDeviceToHost, s));

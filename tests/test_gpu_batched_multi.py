@@ -142,3 +142,20 @@ def test_grad_batched_equals_per_pair_grad(dtype):
         assert float((gmus[i] - a).abs().max()) <= tol * float(a.abs().max())
         assert float((gnus[i] - b).abs().max()) <= tol * float(b.abs().max())
         assert abs(float(gmus[i].double().sum())) <= 1e-6 * float(gmus[i].double().abs().sum())
+
+
+def test_multi_batched_compaction_matches_plain():
+    """70 pairs over two chunks whose stop iterations spread from 2 to 40
+    (the float64 oracle gives 40 of them stopped by iteration 4 at this
+    tolerance): after the replay where at most half are still running, the
+    tables are rebuilt over the running pairs alone (one chunk) and the graph
+    is captured again.  Every pair must still match its own plain solve."""
+    rng = np.random.default_rng(23)
+    shapes = [tuple(int(x) for x in rng.choice([16, 24, 32, 48, 64], size=2)) for _ in range(70)]
+    ps = pairs(shapes, seed=29)
+    mus = [cuda(m) for m, _ in ps]
+    nus = [cuda(n) for _, n in ps]
+    rb = bfm.solve_batched(mus, nus, max_iters=40, tol=1e-3, iters_per_graph=2, return_map=True)
+    _compare(rb, mus, nus, 40, torch.float64, tol=1e-3)
+    its = sorted(r.iters for r in rb)
+    assert its[35] <= 6 and its[-1] == 40, its
