@@ -273,6 +273,40 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     }
 }
 
+// The same line transform for short lines, by the definition itself: the
+// minimum over every point k of the line of (1/2)((j - k) h)^2 + v_k, each
+// candidate in the arithmetic of the hull path's step 5.  Its cost is n
+// candidates per output, but no step depends on an LDS result of the one
+// before, where the hull scan and merges are chains of dependent LDS reads;
+// for a line of a few hundred points the direct minimum finishes first.  The
+// line's values must be staged in v and visible to this lane, and u must
+// hold this lane's own values.
+template <typename T, int C>
+__device__ __forceinline__ void ct_line_direct(T (&u)[C], const T *v, int j0, int j1, int n, T h)
+{
+    T best[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) best[c] = T(INFINITY);
+    for (int k0 = 0; k0 < n; k0 += 16) {       // padi: one pad slot after every 16 values
+        const T *vk = v + padi(k0);
+        const int kn = min(16, n - k0);
+#pragma unroll 4
+        for (int q = 0; q < kn; ++q) {
+            const T val = vk[q];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T d = T(j0 + c - (k0 + q)) * h;
+                best[c] = fmin(best[c], T(0.5) * d * d + val);
+            }
+        }
+    }
+    // u still holds this lane's inputs: a non-finite input stays visible in
+    // its own outputs (the minimum alone would pass over a NaN)
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (j0 + c < j1) u[c] = best[c] + (u[c] - u[c]);
+}
+
 // One group of LPB lines per workgroup: any line length, stride or alignment.
 template <typename T, int C, int LPB>
 __global__ void __launch_bounds__(ct_max_threads(C, LPB))
@@ -786,6 +820,9 @@ constexpr int kMultiCtThreads = 256;
 constexpr int kMultiCtC = 16;        // lines longer than kMultiCtShort points
 constexpr int kMultiCtCShort = 4;    // lines of at most kMultiCtShort points
 constexpr int kMultiCtShort = 256;
+constexpr int kMultiCtDirect = 256;  // lines this short take the direct minimum
+static_assert(kMultiCtDirect <= kMultiCtShort && kMultiCtShort <= kMultiCtCShort * kWave,
+              "direct lines lie inside one wave (line_sync is a wave barrier)");
 
 __host__ __device__ inline int multi_c(int n) { return n <= kMultiCtShort ? kMultiCtCShort : kMultiCtC; }
 
@@ -899,7 +936,12 @@ __device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &
         for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
     }
 
-    ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, T(1.0) / T(n));
+    if (n <= kMultiCtDirect) {   // uniform: one pair per workgroup
+        if (!STRIDED) line_sync(tpl);   // the line's values, staged by its other lanes
+        ct_line_direct<T, C>(u, v, j0, j1, n, T(1.0) / T(n));
+    } else {
+        ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, T(1.0) / T(n));
+    }
 
     double dacc = 0.0;
     if (!STRIDED) {

@@ -133,15 +133,29 @@ __device__ __forceinline__ void small_dft(cpx<T> *x) {
     }
 }
 
+// tab[i] of a table in global memory, read with a global (not flat) load: a
+// pointer argument of an out-of-line function carries no address space.
+template <typename T>
+__device__ __forceinline__ cpx<T> global_cpx(const cpx<T> *tab, int i) {
+    using G = const T __attribute__((address_space(1)));
+    const G *q = (const G *)tab;
+    return {q[2 * i], q[2 * i + 1]};
+}
+
 // One Stockham stage on a padded LDS line (kept out of line: inlining all
-// stages of a transform into one body multiplies its register footprint):
-// butterflies i = lt + q * bd
+// stages of a transform into one body multiplies its register footprint).
+// The line starts `off` complex values into the workgroup's dynamic LDS: a
+// pointer argument would reach an out-of-line function as a generic address
+// and every access would become a flat instruction instead of an LDS one.
+// Butterflies i = lt + q * bd
 // (i < n/R), k = i mod p, inputs buf[i + t n/R], twiddle exp(-2 pi i t k/(p R)),
 // outputs at (i - k) R + k + t p.  All reads of the block complete before any
 // write (barrier); lines of one workgroup advance together.
 template <typename T, int VMAX, int R>
-__device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, int lt, int bd,
-                                          const cpx<T> *__restrict__ tw) {
+__device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int lt, int bd,
+                                                    const cpx<T> *__restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem) + off;
     constexpr int NB = (VMAX + R - 1) / R;
     const int m = n / R;
     const int tstep = n / (p * R);
@@ -154,7 +168,7 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
     for (int q = 0; q < NB; ++q) {
         const int i = lt + q * bd;
         w1[q] = {T(1), T(0)};
-        if (R >= 4 && p > 1 && i < m) w1[q] = tw[(i % p) * tstep];
+        if (R >= 4 && p > 1 && i < m) w1[q] = global_cpx(tw, (i % p) * tstep);
     }
     cpx<T> x[NB][R];
 #pragma unroll
@@ -182,7 +196,7 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
                 }
             } else {
 #pragma unroll
-                for (int t = 1; t < R; ++t) x[q][t] = cmul(x[q][t], tw[t * k * tstep]);
+                for (int t = 1; t < R; ++t) x[q][t] = cmul(x[q][t], global_cpx(tw, t * k * tstep));
             }
             small_dft<T, R>(x[q]);
             const int j = (i - k) * R + k;
@@ -197,33 +211,33 @@ __device__ __attribute__((noinline)) void fft_stage(cpx<T> *buf, int n, int p, i
 // n3 << 24 (stages in that order); one loop per radix keeps each stage's
 // register footprint separate.
 template <typename T, int VMAX>
-__device__ void fft_lds(cpx<T> *buf, int n, uint32_t radices, int lt, int bd, const cpx<T> *__restrict__ tw) {
+__device__ void fft_lds(int off, int n, uint32_t radices, int lt, int bd, const cpx<T> *__restrict__ tw) {
     const int n16 = radices & 63, n8 = (radices >> 6) & 63, n4 = (radices >> 12) & 63;
     const int n2 = (radices >> 18) & 63, n3 = (radices >> 24) & 63;
     int p = 1;
 #pragma unroll 1
     for (int s = 0; s < n16; ++s) {
-        fft_stage<T, VMAX, 16>(buf, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 16>(off, n, p, lt, bd, tw);
         p *= 16;
     }
 #pragma unroll 1
     for (int s = 0; s < n8; ++s) {
-        fft_stage<T, VMAX, 8>(buf, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 8>(off, n, p, lt, bd, tw);
         p *= 8;
     }
 #pragma unroll 1
     for (int s = 0; s < n4; ++s) {
-        fft_stage<T, VMAX, 4>(buf, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 4>(off, n, p, lt, bd, tw);
         p *= 4;
     }
 #pragma unroll 1
     for (int s = 0; s < n2; ++s) {
-        fft_stage<T, VMAX, 2>(buf, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 2>(off, n, p, lt, bd, tw);
         p *= 2;
     }
 #pragma unroll 1
     for (int s = 0; s < n3; ++s) {
-        fft_stage<T, VMAX, 3>(buf, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 3>(off, n, p, lt, bd, tw);
         p *= 3;
     }
 }
@@ -244,17 +258,25 @@ struct DctArgs {
 
 enum DctMode { DM_FWD = kDctFwd, DM_INV = kDctInv, DM_FUSED = kDctFused };
 
+// This lane's entries tab[k0 + q step] (q < Q; indices past the line clamp
+// to its last entry): every load is issued before the first is used, so the
+// lane waits for the table once rather than once per index.
+template <typename V, int Q>
+__device__ __forceinline__ void lane_table(V (&out)[Q], const V *__restrict__ tab, int k0, int step, int n) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = tab[min(k0 + q * step, n - 1)];
+}
+
 // After a forward FFT of z = v_a + i v_b in buf, the DCT-II coefficients of
 // lines a and b at index k.
 template <typename T>
-__device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, const cpx<T> *__restrict__ qw, T &Xa,
-                                          T &Xb) {
+__device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, cpx<T> w, T &Xa, T &Xb) {
     const cpx<T> z = buf[padc(k)];
     const cpx<T> zc = conj_(buf[padc(k == 0 ? 0 : n - k)]);
     const cpx<T> va = {T(0.5) * (z.x + zc.x), T(0.5) * (z.y + zc.y)};
     const cpx<T> dd = csub(z, zc);
     const cpx<T> vb = {T(0.5) * dd.y, T(-0.5) * dd.x};
-    const cpx<T> w = qw[k];   // exp(-i pi k / (2n))
+    // w = qw[k] = exp(-i pi k / (2n))
     Xa = w.x * va.x - w.y * va.y;
     Xb = w.x * vb.x - w.y * vb.y;
 }
@@ -262,10 +284,10 @@ __device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, const
 // Before an inverse: from coefficients (X_a[k], X_b[k]) staged in buf, the
 // conjugate of Z_k = e^{i pi k/(2n)} ((X_a[k] - i X_a[n-k]) + i (X_b[k] - i X_b[n-k])).
 template <typename T>
-__device__ __forceinline__ cpx<T> dct3_pre(const cpx<T> *buf, int n, int k, const cpx<T> *__restrict__ qw) {
+__device__ __forceinline__ cpx<T> dct3_pre(const cpx<T> *buf, int n, int k, cpx<T> qk) {
     const cpx<T> xk = buf[padc(k)];
     const cpx<T> xr = k == 0 ? cpx<T>{T(0), T(0)} : buf[padc(n - k)];
-    const cpx<T> w = conj_(qw[k]);
+    const cpx<T> w = conj_(qk);   // qk = qw[k]
     const cpx<T> wa = {xk.x, -xr.x}, wb = {xk.y, -xr.y};
     const cpx<T> va = cmul(w, wa), vb = cmul(w, wb);
     return conj_(cpx<T>{va.x - vb.y, va.y + vb.x});
@@ -375,11 +397,13 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
             }
         }
         __syncthreads();
+        cpx<T> wq[VMAX];
+        lane_table(wq, qw, lt, bd, n);
         cpx<T> zr[VMAX];
 #pragma unroll
         for (int q = 0; q < VMAX; ++q) {
             const int k = lt + q * bd;
-            if (k < n) zr[q] = dct3_pre(buf, n, k, qw);
+            if (k < n) zr[q] = dct3_pre(buf, n, k, wq[q]);
         }
         __syncthreads();
 #pragma unroll
@@ -490,7 +514,7 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
         }
     }
     __syncthreads();
-    fft_lds<T, VMAX>(buf, n, ax.radices, lt, bd, tw);
+    fft_lds<T, VMAX>(pr * NPC, n, ax.radices, lt, bd, tw);
 
     double gacc = 0.0;
     if (MODE == DM_FUSED) {
@@ -509,15 +533,20 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
                 if (s == 0) { lra = lr; wra = wr; } else { lrb = lr; wrb = wr; }
             }
         }
+        cpx<T> wq[VMAX];
+        T l0v[VMAX];
+        lane_table(wq, qw, lt, bd, n);
+        lane_table(l0v, lam0, lt, bd, n);
+        const double inv_n = 1.0 / n;   // c / n == c * (1 / n) exactly for c = 1, 2
 #pragma unroll
         for (int q = 0; q < VMAX; ++q) {
             const int k = lt + q * bd;
             if (k < n) {
                 T Xa, Xb;
-                dct2_post(buf, n, k, qw, Xa, Xb);
-                const T l0 = lam0[k];
+                dct2_post(buf, n, k, wq[q], Xa, Xb);
+                const T l0 = l0v[q];
                 const T la = l0 + lra, lb = l0 + lrb;
-                const double wk = (k == 0 ? 1.0 : 2.0) / n;
+                const double wk = (k == 0 ? 1.0 : 2.0) * inv_n;
                 ya[q] = la > T(0) ? Xa / la : T(0);
                 yb[q] = lb > T(0) ? Xb / lb : T(0);
                 if (hasa) gacc += wk * wra * (double)Xa * (double)ya[q];
@@ -535,7 +564,7 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
 #pragma unroll
         for (int q = 0; q < VMAX; ++q) {
             const int k = lt + q * bd;
-            if (k < n) zr[q] = dct3_pre(buf, n, k, qw);
+            if (k < n) zr[q] = dct3_pre(buf, n, k, wq[q]);
         }
         __syncthreads();
 #pragma unroll
@@ -544,7 +573,7 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
             if (k < n) buf[padc(k)] = zr[q];
         }
         __syncthreads();
-        fft_lds<T, VMAX>(buf, n, ax.radices, lt, bd, tw);
+        fft_lds<T, VMAX>(pr * NPC, n, ax.radices, lt, bd, tw);
     }
 
     // --------------------------------------------------------------- store
@@ -552,12 +581,19 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
         if (CONTIG) {
             const long long ba = La * n, bbb = Lb * n;
             const bool vec = (n & 3) == 0 && al16;
-            for (int k4 = lt * 4; k4 < n; k4 += bd * 4) {
+            // n <= 16 bd: at most kContigIt groups of four per lane
+            cpx<T> wq[kContigIt][4];
+#pragma unroll
+            for (int it = 0; it < kContigIt; ++it) lane_table(wq[it], qw, (lt + it * bd) * 4, 1, n);
+#pragma unroll
+            for (int it = 0; it < kContigIt; ++it) {
+                const int k4 = (lt + it * bd) * 4;
+                if (k4 >= n) break;
                 T Xa[4], Xb[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     Xa[e] = Xb[e] = T(0);
-                    if (k4 + e < n) dct2_post(buf, n, k4 + e, qw, Xa[e], Xb[e]);
+                    if (k4 + e < n) dct2_post(buf, n, k4 + e, wq[it][e], Xa[e], Xb[e]);
                 }
                 if (vec) {
                     typename v4t<T>::type oa, ob;
@@ -581,10 +617,16 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
                 // thread owns (pair, k): gather both pairs through registers
                 cpx<T> *buf0 = reinterpret_cast<cpx<T> *>(smem);
                 cpx<T> *buf1 = buf0 + NPC;
-                for (int k = threadIdx.x; k < n; k += blockDim.x) {
+                // n <= 16 bd = 8 blockDim: at most kStridedIt indices per lane
+                cpx<T> wq[kStridedIt];
+                lane_table(wq, qw, (int)threadIdx.x, (int)blockDim.x, n);
+#pragma unroll
+                for (int it = 0; it < kStridedIt; ++it) {
+                    const int k = threadIdx.x + it * blockDim.x;
+                    if (k >= n) break;
                     T a0, b0v, a1, b1v;
-                    dct2_post(buf0, n, k, qw, a0, b0v);
-                    dct2_post(buf1, n, k, qw, a1, b1v);
+                    dct2_post(buf0, n, k, wq[it], a0, b0v);
+                    dct2_post(buf1, n, k, wq[it], a1, b1v);
                     typename v4t<T>::type o;
                     o.x = a0; o.y = b0v; o.z = a1; o.w = b1v;
                     *reinterpret_cast<typename v4t<T>::type *>(out + b0 + (long long)k * inner) = o;
@@ -592,7 +634,7 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
             } else {
                 for (int k = lt; k < n; k += bd) {
                     T Xa, Xb;
-                    dct2_post(buf, n, k, qw, Xa, Xb);
+                    dct2_post(buf, n, k, qw[k], Xa, Xb);
                     if (hasa) out[line_base(La, n, inner) + (long long)k * inner] = Xa;
                     if (hasb) out[line_base(Lb, n, inner) + (long long)k * inner] = Xb;
                 }

