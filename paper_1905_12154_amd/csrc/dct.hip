@@ -150,15 +150,17 @@ __device__ __forceinline__ cpx<T> global_cpx(const cpx<T> *tab, int i) {
 // Butterflies i = lt + q * bd
 // (i < n/R), k = i mod p, inputs buf[i + t n/R], twiddle exp(-2 pi i t k/(p R)),
 // outputs at (i - k) R + k + t p.  All reads of the block complete before any
-// write (barrier); lines of one workgroup advance together.
+// write (barrier); lines of one workgroup advance together.  tstep = n / (p R)
+// comes from the caller; the radix-3 stages run last, so p is a power of two
+// in every other stage and k = i mod p is a mask there.
 template <typename T, int VMAX, int R>
-__device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int lt, int bd,
+__device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int tstep, int lt, int bd,
                                                     const cpx<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem[];
     cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem) + off;
     constexpr int NB = (VMAX + R - 1) / R;
     const int m = n / R;
-    const int tstep = n / (p * R);
+    auto kmod = [p](int i) { return R == 3 ? i % p : (i & (p - 1)); };
     // twiddles w^t, w = exp(-2 pi i k / (p R)): for radix 4, 8 and 16 one
     // table load of w and powers by products (w^2t = (w^t)^2,
     // w^(t+1) = w^t w: at most 6 products deep); the first stage (p = 1)
@@ -168,7 +170,7 @@ __device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int l
     for (int q = 0; q < NB; ++q) {
         const int i = lt + q * bd;
         w1[q] = {T(1), T(0)};
-        if (R >= 4 && p > 1 && i < m) w1[q] = global_cpx(tw, (i % p) * tstep);
+        if (R >= 4 && p > 1 && i < m) w1[q] = global_cpx(tw, kmod(i) * tstep);
     }
     cpx<T> x[NB][R];
 #pragma unroll
@@ -184,7 +186,7 @@ __device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int l
     for (int q = 0; q < NB; ++q) {
         const int i = lt + q * bd;
         if (i < m) {
-            const int k = i % p;
+            const int k = kmod(i);
             if constexpr (R >= 4) {
                 if (p > 1) {
                     cpx<T> wp[R];
@@ -214,31 +216,36 @@ template <typename T, int VMAX>
 __device__ void fft_lds(int off, int n, uint32_t radices, int lt, int bd, const cpx<T> *__restrict__ tw) {
     const int n16 = radices & 63, n8 = (radices >> 6) & 63, n4 = (radices >> 12) & 63;
     const int n2 = (radices >> 18) & 63, n3 = (radices >> 24) & 63;
-    int p = 1;
+    int p = 1, rest = n;   // rest = n / p
 #pragma unroll 1
     for (int s = 0; s < n16; ++s) {
-        fft_stage<T, VMAX, 16>(off, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 16>(off, n, p, rest / 16, lt, bd, tw);
         p *= 16;
+        rest /= 16;
     }
 #pragma unroll 1
     for (int s = 0; s < n8; ++s) {
-        fft_stage<T, VMAX, 8>(off, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 8>(off, n, p, rest / 8, lt, bd, tw);
         p *= 8;
+        rest /= 8;
     }
 #pragma unroll 1
     for (int s = 0; s < n4; ++s) {
-        fft_stage<T, VMAX, 4>(off, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 4>(off, n, p, rest / 4, lt, bd, tw);
         p *= 4;
+        rest /= 4;
     }
 #pragma unroll 1
     for (int s = 0; s < n2; ++s) {
-        fft_stage<T, VMAX, 2>(off, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 2>(off, n, p, rest / 2, lt, bd, tw);
         p *= 2;
+        rest /= 2;
     }
 #pragma unroll 1
     for (int s = 0; s < n3; ++s) {
-        fft_stage<T, VMAX, 3>(off, n, p, lt, bd, tw);
+        fft_stage<T, VMAX, 3>(off, n, p, rest / 3, lt, bd, tw);
         p *= 3;
+        rest /= 3;
     }
 }
 
@@ -269,6 +276,17 @@ __device__ __forceinline__ void lane_table(V (&out)[Q], const V *__restrict__ ta
 
 // After a forward FFT of z = v_a + i v_b in buf, the DCT-II coefficients of
 // lines a and b at index k.
+// z = buf[k], zr = buf[n - k] (buf[0] for k = 0), w = qw[k].
+template <typename T>
+__device__ __forceinline__ void dct2_post_v(cpx<T> z, cpx<T> zr, cpx<T> w, T &Xa, T &Xb) {
+    const cpx<T> zc = conj_(zr);
+    const cpx<T> va = {T(0.5) * (z.x + zc.x), T(0.5) * (z.y + zc.y)};
+    const cpx<T> dd = csub(z, zc);
+    const cpx<T> vb = {T(0.5) * dd.y, T(-0.5) * dd.x};
+    Xa = w.x * va.x - w.y * va.y;
+    Xb = w.x * vb.x - w.y * vb.y;
+}
+
 template <typename T>
 __device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, cpx<T> w, T &Xa, T &Xb) {
     const cpx<T> z = buf[padc(k)];
@@ -283,6 +301,15 @@ __device__ __forceinline__ void dct2_post(const cpx<T> *buf, int n, int k, cpx<T
 
 // Before an inverse: from coefficients (X_a[k], X_b[k]) staged in buf, the
 // conjugate of Z_k = e^{i pi k/(2n)} ((X_a[k] - i X_a[n-k]) + i (X_b[k] - i X_b[n-k])).
+// xk = (X_a[k], X_b[k]), xr = (X_a[n-k], X_b[n-k]) (zero for k = 0), qk = qw[k].
+template <typename T>
+__device__ __forceinline__ cpx<T> dct3_pre_v(cpx<T> xk, cpx<T> xr, cpx<T> qk) {
+    const cpx<T> w = conj_(qk);
+    const cpx<T> wa = {xk.x, -xr.x}, wb = {xk.y, -xr.y};
+    const cpx<T> va = cmul(w, wa), vb = cmul(w, wb);
+    return conj_(cpx<T>{va.x - vb.y, va.y + vb.x});
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> dct3_pre(const cpx<T> *buf, int n, int k, cpx<T> qk) {
     const cpx<T> xk = buf[padc(k)];
@@ -518,8 +545,11 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
 
     double gacc = 0.0;
     if (MODE == DM_FUSED) {
-        // coefficients along this axis, divided by lambda; restage for the inverse
-        T ya[VMAX], yb[VMAX];
+        // coefficients along this axis, divided by lambda, and the inverse's
+        // input: each lane takes index pairs {u, n - u} (u = 0 .. n/2), whose
+        // two FFT values give the coefficients at both indices and whose two
+        // divided coefficients give the inverse's input at both, so the
+        // divided coefficients never pass through LDS
         // eigenvalue and weight of the other axes for lines a and b
         T lra = T(0), lrb = T(0);
         double wra = 1.0, wrb = 1.0;
@@ -527,50 +557,54 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
             const long long Ls[2] = {La, Lb};
             for (int s = 0; s < 2; ++s) {
                 const long long Lx = Ls[s] < ax.nlines ? Ls[s] : 0;
-                const int kA = (int)(Lx / ax.nB), kB = (int)(Lx % ax.nB);
+                const int kA = ax.nB == 1 ? (int)Lx : (int)(Lx / ax.nB), kB = ax.nB == 1 ? 0 : (int)(Lx % ax.nB);
                 const T lr = lamA[kA] + (ax.nB > 1 ? lamB[kB] : T(0));
                 const double wr = ((kA == 0) ? 1.0 : 2.0) / ax.nA * (ax.nB > 1 ? ((kB == 0) ? 1.0 : 2.0) / ax.nB : 1.0);
                 if (s == 0) { lra = lr; wra = wr; } else { lrb = lr; wrb = wr; }
             }
         }
-        cpx<T> wq[VMAX];
-        T l0v[VMAX];
-        lane_table(wq, qw, lt, bd, n);
-        lane_table(l0v, lam0, lt, bd, n);
+        constexpr int QU = VMAX / 2 + 1;   // n <= VMAX bd: n/2 + 1 <= QU bd pairs
+        const int half = n / 2;
+        cpx<T> wq1[QU], wq2[QU];
+        T l01[QU], l02[QU];
+        lane_table(wq1, qw, lt, bd, n);
+        lane_table(l01, lam0, lt, bd, n);
+#pragma unroll
+        for (int q = 0; q < QU; ++q) {   // partner indices n - u (u = 0: itself)
+            const int u = min(lt + q * bd, half);
+            const int k2 = u == 0 ? 0 : n - u;
+            wq2[q] = qw[k2];
+            l02[q] = lam0[k2];
+        }
         const double inv_n = 1.0 / n;   // c / n == c * (1 / n) exactly for c = 1, 2
+        // buf[u] and buf[n - u] are read and written by this lane alone:
+        // each pair goes back in place without a barrier
 #pragma unroll
-        for (int q = 0; q < VMAX; ++q) {
-            const int k = lt + q * bd;
-            if (k < n) {
-                T Xa, Xb;
-                dct2_post(buf, n, k, wq[q], Xa, Xb);
-                const T l0 = l0v[q];
-                const T la = l0 + lra, lb = l0 + lrb;
-                const double wk = (k == 0 ? 1.0 : 2.0) * inv_n;
-                ya[q] = la > T(0) ? Xa / la : T(0);
-                yb[q] = lb > T(0) ? Xb / lb : T(0);
-                if (hasa) gacc += wk * wra * (double)Xa * (double)ya[q];
-                if (hasb) gacc += wk * wrb * (double)Xb * (double)yb[q];
+        for (int q = 0; q < QU; ++q) {
+            const int u = lt + q * bd;
+            if (u <= half) {
+                const bool self = u == 0 || 2 * u == n;   // n - u is u itself (or k = 0)
+                const cpx<T> z1 = buf[padc(u)], z2 = buf[padc(u == 0 ? 0 : n - u)];
+                T Xa1, Xb1, Xa2, Xb2;
+                dct2_post_v(z1, z2, wq1[q], Xa1, Xb1);
+                dct2_post_v(z2, z1, wq2[q], Xa2, Xb2);
+                const T la1 = l01[q] + lra, lb1 = l01[q] + lrb;
+                const T la2 = l02[q] + lra, lb2 = l02[q] + lrb;
+                const T ya1 = la1 > T(0) ? Xa1 / la1 : T(0), yb1 = lb1 > T(0) ? Xb1 / lb1 : T(0);
+                const T ya2 = la2 > T(0) ? Xa2 / la2 : T(0), yb2 = lb2 > T(0) ? Xb2 / lb2 : T(0);
+                const double wk1 = (u == 0 ? 1.0 : 2.0) * inv_n, wk2 = 2.0 * inv_n;
+                if (hasa) gacc += wk1 * wra * (double)Xa1 * (double)ya1;
+                if (hasb) gacc += wk1 * wrb * (double)Xb1 * (double)yb1;
+                if (!self) {
+                    if (hasa) gacc += wk2 * wra * (double)Xa2 * (double)ya2;
+                    if (hasb) gacc += wk2 * wrb * (double)Xb2 * (double)yb2;
+                }
+                const cpx<T> y1 = {ya1, yb1}, y2 = {ya2, yb2};
+                // the inverse's input at u (no partner coefficient at k = 0)
+                // and at n - u
+                buf[padc(u)] = dct3_pre_v(y1, u == 0 ? cpx<T>{T(0), T(0)} : (self ? y1 : y2), wq1[q]);
+                if (!self) buf[padc(n - u)] = dct3_pre_v(y2, y1, wq2[q]);
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < VMAX; ++q) {
-            const int k = lt + q * bd;
-            if (k < n) buf[padc(k)] = {ya[q], yb[q]};
-        }
-        __syncthreads();
-        cpx<T> zr[VMAX];
-#pragma unroll
-        for (int q = 0; q < VMAX; ++q) {
-            const int k = lt + q * bd;
-            if (k < n) zr[q] = dct3_pre(buf, n, k, wq[q]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < VMAX; ++q) {
-            const int k = lt + q * bd;
-            if (k < n) buf[padc(k)] = zr[q];
         }
         __syncthreads();
         fft_lds<T, VMAX>(pr * NPC, n, ax.radices, lt, bd, tw);
