@@ -222,6 +222,7 @@ def c4_leg(iters, autotune):
     rw = plan.solve(mu, nu, return_map=False)   # warm-up (same work)
     if autotune:
         plan.autotune(dev, sample=rw.phi)
+        plan.autotune_deposit(rw.phi, mu)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = plan.solve(mu, nu, return_map=False)
@@ -232,7 +233,7 @@ def c4_leg(iters, autotune):
     gbs = ITER_BYTES_PER_POINT[3] * N / (ms * 1e-3) / 1e9
     return {"workload": "c4: 3D 384^3, 6-Gaussian mixtures, float32", "iters": r.iters, "seconds": dt,
             "ms_per_iter": ms, "pts_iters_per_s": N * r.iters / dt, "gap": r.gap,
-            "dual": r.dual, "tuning": plan.tuning(),
+            "dual": r.dual, "tuning": plan.tuning(), "deposit_grid": plan.deposit_grid(),
             "roofline": {"bound": "hbm", "model_bytes_per_point_iter": ITER_BYTES_PER_POINT[3],
                          "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "iteration_frac": gbs / HBM_PEAK_GBS}}
@@ -593,6 +594,8 @@ def main():
     plan = bfm.Plan((n, n), torch.float32, max_iters=args.steps, check_every=max(args.steps, 1))
     # launch shapes tuned on the warm-up potential (what the timed solve sees)
     tuning = plan.autotune(dev, sample=rw.phi) if not args.no_autotune else None
+    # the deposition's workgroup count, timed on the same potential and mu
+    deposit_grid = plan.autotune_deposit(rw.phi, mu) if not args.no_autotune else plan.deposit_grid()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = plan.solve(mu, nu, phi_init=rw.phi, return_map=False)
@@ -604,6 +607,7 @@ def main():
     gplan = bfm.Plan((n, n), torch.float32, max_iters=args.gap_iters, tol=1e-4, check_every=4)
     if not args.no_autotune:
         gplan.autotune(dev)   # reuses the table filled above
+    gplan.set_deposit_grid(deposit_grid)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     rg = gplan.solve(mu, nu, return_map=False)
@@ -647,6 +651,7 @@ def main():
                      "iteration_frac": ITER_BYTES_PER_POINT[2] * N / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kt,
         "tuning": tuning,
+        "deposit_grid": deposit_grid,
         "dual": r.dual,
         "gap": r.gap,
     }

@@ -215,6 +215,23 @@ bfm_status bfm_plan_tuning(bfm_plan plan, int32_t *cfg9);
  * later calls fail with BFM_EDEVICE. */
 bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9);
 
+/* Deposition workgroups (the pushforward of Section 2.1 on the grid): the
+ * deposition walks the source tiles that hold mass with this many
+ * workgroups.  0 restores the built-in count (one per 8^3 or 16 x 32 tile, at
+ * most 2048); otherwise a multiple of 8 from 8 to 8192.  BFM_EINVAL outside
+ * that.  The count changes only the order of the float64 partial sums. */
+bfm_status bfm_plan_set_deposit_grid(bfm_plan plan, int32_t workgroups);
+bfm_status bfm_plan_deposit_grid(bfm_plan plan, int32_t *workgroups);
+
+/* Times the deposition with 1024, 2048, 4096 and 8192 workgroups (those not
+ * above the tile count rounded up to a multiple of 8) on phi^c of `phi` and
+ * the density `mass` (N device elements each; mass as the solver walks it:
+ * its tiles with mass only), and keeps the fastest in the plan.  The best
+ * count depends on the density's support and the map, so the caller passes
+ * the problem's own.  Synchronises `stream`; overwrites the workspace. */
+bfm_status bfm_autotune_deposit(bfm_plan plan, const void *phi, const void *mass, void *workspace, size_t ws_bytes,
+                                void *stream);
+
 /* Displacement interpolation (Section 4.3, optimal transport of images):
  * for each time t_k in [0, 1],
  *   rho_k = S_t # mu,  S_t(x) = t T(x) + (1 - t) x,  T(x) = x - grad phi^c(x),

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "BFM_OK", 1: "BFM_EINVAL", 2: "BFM_EDEVICE", 3: "BFM_ENUMERIC
 EXPORTED = ["bfm_params_init", "bfm_plan_create", "bfm_plan_destroy", "bfm_plan_workspace_bytes", "bfm_solve",
             "bfm_ctransform", "bfm_pushforward", "bfm_poisson_neumann", "bfm_grad", "bfm_last_error",
             "bfm_version", "bfm_ctransform_axis", "bfm_trace", "bfm_solve_batched", "bfm_autotune",
-            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_ctransform_pass", "bfm_interpolate",
+            "bfm_plan_tuning", "bfm_plan_set_tuning", "bfm_plan_set_deposit_grid", "bfm_plan_deposit_grid",
+            "bfm_autotune_deposit", "bfm_ctransform_pass", "bfm_interpolate",
             "bfm_solve_noalloc", "bfm_grad_batched"]
 
 
@@ -84,6 +85,9 @@ def lib():
         L.bfm_autotune.argtypes = [vp, vp, vp, sz, vp]
         L.bfm_plan_tuning.argtypes = [vp, P(i32)]
         L.bfm_plan_set_tuning.argtypes = [vp, P(i32)]
+        L.bfm_plan_set_deposit_grid.argtypes = [vp, i32]
+        L.bfm_plan_deposit_grid.argtypes = [vp, P(i32)]
+        L.bfm_autotune_deposit.argtypes = [vp, vp, vp, vp, sz, vp]
         L.bfm_ctransform_pass.argtypes = [vp, i32, vp, vp, vp, P(ctypes.c_double), vp, sz, vp]
         L.bfm_interpolate.argtypes = [vp, vp, vp, i32, P(ctypes.c_double), vp, vp, sz, vp]
         L.bfm_solve_batched.argtypes = [i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp), P(sz), i32, vp,
@@ -232,6 +236,26 @@ class Plan:
             for k in range(3):
                 flat[3 * a + k] = int(tri[k])
         _check(lib().bfm_plan_set_tuning(self._h, flat))
+
+    def autotune_deposit(self, phi, mass):
+        """Time the deposition's workgroup counts on phi^c of ``phi`` and the
+        density ``mass`` (the problem's own: the best count depends on its
+        support and map) and keep the fastest; returns the count."""
+        phi = self._field(phi, "phi")
+        mass = self._field(mass, "mass")
+        ws = self.workspace(mass.device)
+        _check(lib().bfm_autotune_deposit(self._h, _ptr(phi), _ptr(mass), _ptr(ws), self.ws_bytes,
+                                          _stream(mass.device)))
+        return self.deposit_grid()
+
+    def deposit_grid(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().bfm_plan_deposit_grid(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_deposit_grid(self, workgroups: int):
+        """Deposition workgroups: 0 (built-in) or a multiple of 8 up to 8192."""
+        _check(lib().bfm_plan_set_deposit_grid(self._h, int(workgroups)))
 
     def interpolate(self, phi, mu, times):
         """Displacement interpolants rho_t = S_t # mu, S_t = t T + (1 - t) id,

@@ -105,7 +105,8 @@ long long dct_fused_parts(int n0, long long N, size_t esz);
 
 // map, pushforward, reductions, controller (pushforward.hip, reduce.hip)
 // tiles (nullable): count followed by the indices of the source tiles with
-// mass, from launch_tile_list; only those tiles are deposited
+// mass, from launch_tile_list; only those tiles are deposited.  nblocks:
+// workgroups (0: splat_blocks); part_* receive one partial per workgroup.
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
                         double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream, T tmix = T(1),
@@ -122,6 +123,7 @@ template <typename T>
 hipError_t launch_stats(const T *mu, const T *nu, long long N, double *partials, long long slot_len, int nblocks,
                         hipStream_t stream);
 long long splat_blocks(const Grid &g);
+constexpr int kMaxDepositGrid = 8192;   // most deposition workgroups a plan's slots hold
 template <typename T>
 hipError_t launch_fill(T *x, long long N, T value, hipStream_t stream);
 template <typename T>

@@ -683,10 +683,10 @@ hipError_t launch_tile_list(const Grid &g, const T *src, int *flags, int *list, 
 
 template <typename T>
 hipError_t launch_splat(const Grid &g, const T *pc, const T *src, T *rho, T *Tout, double *part_primal,
-                        double *part_pcsrc, int /*nblocks*/, const int32_t *done, hipStream_t stream, T tmix,
+                        double *part_pcsrc, int nblocks, const int32_t *done, hipStream_t stream, T tmix,
                         const int *tiles)
 {
-    const long long nb = splat_blocks(g), nt = splat_ntiles(g);
+    const long long nb = nblocks > 0 ? nblocks : splat_blocks(g), nt = splat_ntiles(g);
     const bool gen = !grid_quadratic(g);
 #define BFM_SPLAT(D_, G_)                                                                                        \
     hipLaunchKernelGGL((splat_kernel<T, D_, G_>), dim3((unsigned)nb), dim3(kRedBlock), 0, stream, g, nt, pc, src, \

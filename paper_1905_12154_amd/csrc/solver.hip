@@ -217,10 +217,10 @@ extern "C" bfm_status bfm_plan_create(const bfm_params *p, bfm_plan *out)
     P->off_state = off;  off = align256(off + sizeof(DevState));
     P->off_trace = off;  off = align256(off + sizeof(TraceRec) * kMaxTrace);
     P->nsplat = (int)splat_blocks(g);
-    // slots hold up to max(deposition workgroups, 4096) partials: the grid-stride
-    // reductions (1024), and the sums fused into the last inverse DCT pass and
-    // the c-transform's second pass when their grids fit
-    P->slot_len = P->nsplat > 4096 ? P->nsplat : 4096;
+    // slots hold kMaxDepositGrid partials: the deposition's (any tuned grid),
+    // the grid-stride reductions (1024), and the sums fused into the last
+    // inverse DCT pass and the c-transform's second pass when their grids fit
+    P->slot_len = kMaxDepositGrid;
     P->off_part = off;   off = align256(off + sizeof(double) * kNumSlots * (size_t)P->slot_len);
     P->gparts = (int)dct_fused_parts(g.n[0], g.N, P->esz);
     P->off_gpart = off;  off = align256(off + sizeof(double) * (size_t)P->gparts);
@@ -399,7 +399,7 @@ static hipError_t half_step(bfm_plan P, const Ws &w, T *p, const T *src, const i
     if (head_dot &&
         (e = launch_dot2<T>(p, tgt, nullptr, nullptr, g.N, w.slot(S_P_TGT), nullptr, nb, done, s)) != hipSuccess)
         return e;
-    if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, done, s, T(1),
+    if ((e = launch_splat<T>(g, pc, src, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), P->nsplat, done, s, T(1),
                              src_tiles)) !=
         hipSuccess)
         return e;
@@ -536,7 +536,7 @@ static hipError_t enqueue_finish(bfm_plan P, const Ws &w, const T *mu, T *phi, T
     T *pc = (T *)w.pc;
     hipError_t e;
     if (Tmap != nullptr &&
-        (e = launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, nb, nullptr, s)) != hipSuccess)
+        (e = launch_splat<T>(g, pc, mu, nullptr, Tmap, nullptr, nullptr, P->nsplat, nullptr, s)) != hipSuccess)
         return e;
     if ((e = launch_dot2<T>(phi, nullptr, nullptr, nullptr, g.N, w.slot(S_MEAN_A), nullptr, nb, nullptr, s)) !=
         hipSuccess)
@@ -1315,6 +1315,76 @@ extern "C" bfm_status bfm_autotune(bfm_plan plan, const void *sample, void *work
     return autotune_impl<float>(plan, (const float *)sample, w, s, 5);
 }
 
+extern "C" bfm_status bfm_plan_set_deposit_grid(bfm_plan plan, int32_t workgroups)
+{
+    if (plan == nullptr) return fail(BFM_EINVAL, "plan is NULL");
+    if (workgroups != 0 && (workgroups < 8 || workgroups > kMaxDepositGrid || workgroups % 8 != 0))
+        return fail(BFM_EINVAL, "deposition workgroups %d: 0, or a multiple of 8 from 8 to %d", workgroups,
+                    kMaxDepositGrid);
+    plan->nsplat = workgroups == 0 ? (int)splat_blocks(plan->g) : workgroups;
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_plan_deposit_grid(bfm_plan plan, int32_t *workgroups)
+{
+    if (plan == nullptr || workgroups == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    *workgroups = plan->nsplat;
+    return BFM_OK;
+}
+
+template <typename T>
+static bfm_status autotune_deposit_impl(bfm_plan P, const T *phi, const T *mass, const Ws &w, hipStream_t s, int reps)
+{
+    const Grid &g = P->g;
+    T *pc = (T *)w.pc, *rho = (T *)w.rho;
+    HIP_TRY(ctransform_field<T>(g, phi, pc, nullptr, s, P->ct_cfg, (T *)w.f));
+    HIP_TRY(launch_tile_list<T>(g, mass, (int *)w.f, w.tiles_mu, s));
+    HIP_TRY(launch_fill<T>(rho, g.N, T(0), s));   // the deposits accumulate over the timed calls
+    const long long tiles8 = (splat_tile_count(g) + 7) / 8 * 8;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    float best = 1e30f;
+    int pick = 0;
+    for (int G : {1024, 2048, 4096, kMaxDepositGrid}) {
+        if (G > tiles8 && G != 1024) continue;
+        const int Gc = (long long)G > tiles8 ? (int)tiles8 : G;
+        hipError_t e = launch_splat<T>(g, pc, mass, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), Gc, nullptr,
+                                       s, T(1), w.tiles_mu);   // warm-up
+        if (e != hipSuccess) continue;
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_splat<T>(g, pc, mass, rho, nullptr, w.slot(S_PRIMAL), w.slot(S_PC_SRC), Gc, nullptr, s, T(1),
+                                w.tiles_mu);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess || e != hipSuccess) continue;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best) {
+            best = ms;
+            pick = Gc;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (pick == 0) return fail(BFM_EDEVICE, "autotune: no deposition grid launched");
+    P->nsplat = pick;
+    return BFM_OK;
+}
+
+extern "C" bfm_status bfm_autotune_deposit(bfm_plan plan, const void *phi, const void *mass, void *workspace,
+                                           size_t ws_bytes, void *stream)
+{
+    if (plan == nullptr || phi == nullptr || mass == nullptr) return fail(BFM_EINVAL, "NULL argument");
+    Ws w;
+    bfm_status st = check_ws(plan, workspace, ws_bytes, &w);
+    if (st != BFM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prm.dtype == BFM_F64)
+        return autotune_deposit_impl<double>(plan, (const double *)phi, (const double *)mass, w, s, 5);
+    return autotune_deposit_impl<float>(plan, (const float *)phi, (const float *)mass, w, s, 5);
+}
+
 extern "C" bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9)
 {
     if (plan == nullptr || cfg9 == nullptr) return fail(BFM_EINVAL, "NULL argument");
@@ -1446,7 +1516,7 @@ static bfm_status interp_impl(bfm_plan P, const T *phi, const T *mu, int nt, con
     for (int k = 0; k < nt; ++k) {
         T *r = rho + (size_t)k * g.N;
         HIP_TRY(launch_fill<T>(r, g.N, T(0), s));
-        HIP_TRY(launch_splat<T>(g, pc, mu, r, nullptr, nullptr, nullptr, P->red_blocks, nullptr, s, (T)times[k]));
+        HIP_TRY(launch_splat<T>(g, pc, mu, r, nullptr, nullptr, nullptr, P->nsplat, nullptr, s, (T)times[k]));
     }
     return BFM_OK;
 }
@@ -1501,9 +1571,8 @@ template <typename T>
 static bfm_status push_impl(bfm_plan P, const T *phic, const T *mass, T *rho, T *Tmap, double *primal,
                             const Ws &w, hipStream_t s)
 {
-    const int nb = P->red_blocks;
     HIP_TRY(launch_fill<T>(rho, P->g.N, T(0), s));
-    HIP_TRY(launch_splat<T>(P->g, phic, mass, rho, Tmap, w.slot(S_PRIMAL), w.slot(S_PC_SRC), nb, nullptr, s));
+    HIP_TRY(launch_splat<T>(P->g, phic, mass, rho, Tmap, w.slot(S_PRIMAL), w.slot(S_PC_SRC), P->nsplat, nullptr, s));
     if (primal != nullptr) {
         std::vector<double> h(P->nsplat);
         HIP_TRY(hipMemcpyAsync(h.data(), w.slot(S_PRIMAL), P->nsplat * sizeof(double), hipMemcpyDeviceToHost, s));

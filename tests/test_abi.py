@@ -179,3 +179,20 @@ def test_grad_batched_validation_before_any_launch():
     assert L.bfm_grad_batched(2, plans, f, f, ones, f, f, shared, sizes, None) == bfm.BFM_EINVAL
     small = (ctypes.c_size_t * 2)(plan.ws_bytes, plan.ws_bytes - 1)
     assert L.bfm_grad_batched(2, plans, f, f, ones, f, f, VP(*ws_ok), small, None) == bfm.BFM_EWORKSPACE
+
+
+def test_deposit_grid_setting_and_validation():
+    # built-in: one workgroup per source tile (16 x 32 in 2D, 8^3 in 3D), at most 2048
+    plan = bfm.Plan((64, 64))
+    assert plan.deposit_grid() == (64 // 16) * (64 // 32)
+    assert bfm.Plan((384, 256)).deposit_grid() == (384 // 16) * (256 // 32)
+    assert bfm.Plan((4096, 4096)).deposit_grid() == 2048
+    assert bfm.Plan((64, 64, 64)).deposit_grid() == 512
+    for bad in (7, 4, -8, 8200, 16384):
+        with pytest.raises(bfm.BFMError) as e:
+            plan.set_deposit_grid(bad)
+        assert e.value.status == bfm.BFM_EINVAL
+    plan.set_deposit_grid(8192)
+    assert plan.deposit_grid() == 8192
+    plan.set_deposit_grid(0)
+    assert plan.deposit_grid() == 8

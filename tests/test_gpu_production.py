@@ -134,3 +134,30 @@ def test_sigma_floor_hits_match_oracle(sigma0, sigma_min):
     assert r.sigma == pytest.approx(o.sigma, rel=1e-12)
     if sigma_min > 1.0:
         assert hits > 0   # steps this large overshoot and are clamped
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (48, 36, 32)])
+def test_deposit_grid_changes_only_the_order_of_sums(shape):
+    """The deposition's workgroup count (set, or picked by
+    bfm_autotune_deposit) changes only how the float64 partial sums are
+    grouped (and the order of the float atomics): same iterations, same
+    results to rounding."""
+    rng = np.random.default_rng(8)
+    mu = wl.random_gaussian_mixture(shape, 3, rng)
+    nu = wl.random_gaussian_mixture(shape, 2, rng)
+    base = bfm.Plan(shape, torch.float64, max_iters=8).solve(cuda(mu), cuda(nu))
+    tuned = bfm.Plan(shape, torch.float64, max_iters=8)
+    picked = tuned.autotune_deposit(base.phi, cuda(mu))
+    tiles = int(np.prod([-(-n // t) for n, t in zip(shape, (16, 32) if len(shape) == 2 else (8, 8, 8))]))
+    assert picked in (1024, 2048, 4096, 8192) or picked == -(-tiles // 8) * 8
+    plans = [tuned]
+    for G in (8, 1024, 8192):
+        p = bfm.Plan(shape, torch.float64, max_iters=8)
+        p.set_deposit_grid(G)
+        plans.append(p)
+    for p in plans:
+        r = p.solve(cuda(mu), cuda(nu))
+        assert r.iters == base.iters
+        assert abs(r.dual - base.dual) <= 1e-11 * abs(base.dual)
+        assert r.sigma == pytest.approx(base.sigma, rel=1e-12)
+        assert float((r.phi - base.phi).abs().max()) <= 1e-9 * float(base.phi.abs().max())
