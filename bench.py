@@ -92,10 +92,11 @@ def parse():
     ap.add_argument("--tuning", default=None,
                     help="launch shapes of the counter leg instead of autotuning, as C,lines,mode per axis "
                          "separated by ';' (the shapes the bench's own run reported)")
-    ap.add_argument("--pmc-leg", nargs="?", const="ct", default=None, choices=["ct", "splat3d"],
+    ap.add_argument("--pmc-leg", nargs="?", const="ct", default=None, choices=["ct", "splat3d", "dct"],
                     help="the program run under rocprofv3 --pmc: 'ct' (default) the dominant kernel's timing "
-                         "leg, 'splat3d' three iterations of the 384^3 workload; each followed by a %d MiB "
-                         "copy for counter calibration" % (COPY_BYTES >> 20))
+                         "leg, 'splat3d' three iterations of the 384^3 workload, 'dct' three iterations of the "
+                         "4096^2 workload; each followed by a %d MiB copy for counter calibration"
+                         % (COPY_BYTES >> 20))
     ap.add_argument("--oracle-c4-iters", type=int, default=1,
                     help="iterations of the 384^3 oracle run of the oracle legs (0 skips it)")
     ap.add_argument("--no-oracle-legs", action="store_true",
@@ -492,6 +493,28 @@ def pmc_splat3d_leg(iters=3):
           flush=True)
 
 
+def pmc_dct_leg(n=4096, iters=3):
+    """What the Poisson-pass counter runs profile: `iters` iterations of the
+    4096^2 float32 headline workload from phi = 0 (per half-step one forward
+    row pass, one fused column pass, one inverse row pass), then one device
+    copy of COPY_BYTES (the calibration kernel)."""
+    import torch
+    from paper_1905_12154_amd import bfm, workloads as wl
+    dev = torch.device("cuda:0")
+    mu_h, nu_h = wl.config_c3(n)
+    mu = torch.tensor(mu_h, dtype=torch.float32, device=dev)
+    nu = torch.tensor(nu_h, dtype=torch.float32, device=dev)
+    del mu_h, nu_h
+    plan = bfm.Plan(mu.shape, torch.float32, max_iters=iters, check_every=iters)
+    r = plan.solve(mu, nu, return_map=False)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_leg": "dct", "iters": r.iters, "dual": r.dual, "copy_bytes": COPY_BYTES}), flush=True)
+
+
 def _map_cells(Tg, To, shape, support):
     """Largest map difference over the axes, in grid cells of each axis, at
     the cells of `support`: mean, median, 99.9th percentile, maximum."""
@@ -580,6 +603,9 @@ def main():
     n = args.n
     if args.pmc_leg == "ct":
         pmc_leg(n, args)
+        return
+    if args.pmc_leg == "dct":
+        pmc_dct_leg()
         return
     if args.pmc_leg == "splat3d":
         pmc_splat3d_leg()
