@@ -97,7 +97,7 @@ def parse():
                          "leg, 'splat3d' three iterations of the 384^3 workload, 'dct' three iterations of the "
                          "4096^2 workload; each followed by a %d MiB copy for counter calibration"
                          % (COPY_BYTES >> 20))
-    ap.add_argument("--oracle-c4-iters", type=int, default=1,
+    ap.add_argument("--oracle-c4-iters", type=int, default=3,
                     help="iterations of the 384^3 oracle run of the oracle legs (0 skips it)")
     ap.add_argument("--no-oracle-legs", action="store_true",
                     help="skip the oracle runs at c1, c2, c4 and on c5 pairs (timing and float32 error)")
