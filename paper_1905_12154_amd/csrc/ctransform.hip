@@ -1014,7 +1014,7 @@ ct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role, int wh
     __shared__ double dred[kMultiCtThreads / kWave];
     const int pr = batch_pair(bi);
     const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[pr];
-    if (P.st->done) return;
+    if ((tab->done_mask >> pr) & 1ull) return;
     if (multi_c(STRIDED ? P.n0 : P.n1) == kMultiCtCShort)
         ct_multi_body<T, STRIDED, kMultiCtCShort>(P, bi, pr, role, which, smem, wave_tot, dred);
     else

@@ -837,7 +837,7 @@ dct_multi_kernel(const BatchHead *__restrict__ tab, BatchIdx bi, int role)
         else hi = mid - 1;
     }
     const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[lo];
-    if (P.st->done) return;
+    if ((tab->done_mask >> lo) & 1ull) return;
     const long long blk = (long long)blockIdx.x - bi.off[lo];
     T *p = (T *)(role ? P.psi : P.phi);
     const T *tgt = (const T *)(role ? P.mu : P.nu);

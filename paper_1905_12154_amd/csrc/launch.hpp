@@ -194,7 +194,7 @@ struct BatchHead {
     int all_done;                     // 1 when every pair's stop flag is set (launch_batch_done)
     int splat_grid;                   // workgroups of the joint deposition launch (host-set)
     int nactive;                      // pairs whose stop flag is clear (launch_batch_done)
-    unsigned long long done_mask;     // bit p: pair p has stopped (launch_batch_done)
+    unsigned long long done_mask;     // bit p: pair p has stopped (set by the controller, launch_batch_done)
 };
 static_assert(sizeof(BatchHead) % 8 == 0, "the pair table after the head stays 8-byte aligned");
 constexpr size_t kBatchTableBytes = sizeof(BatchHead) + kBatchChunk * sizeof(PairDev);
@@ -218,7 +218,7 @@ constexpr int kDctFwd = 0, kDctInv = 1, kDctFused = 2;
 template <typename T>
 hipError_t launch_dct_multi(const BatchHead *tab, const int *n0s, const int *n1s, int np, int role, int mode,
                             hipStream_t stream);
-hipError_t launch_ctrl_multi(const BatchHead *tab, int np, int role, int mode, hipStream_t stream);
+hipError_t launch_ctrl_multi(BatchHead *tab, int np, int role, int mode, hipStream_t stream);
 hipError_t launch_batch_done(BatchHead *tab, hipStream_t stream);
 // Batched W2^2 gradient: per pair, the potentials' sums (one partial per
 // workgroup into S_MEAN_A (psi) and S_MEAN_B (phi)), the means (one workgroup

@@ -465,7 +465,7 @@ splat_multi_kernel(const BatchHead *__restrict__ tab, int role)
             cur = p;
             first = k;
             const PairDev &Q = pairs[p];
-            skip = Q.st->done != 0;
+            skip = ((tab->done_mask >> p) & 1ull) != 0;
             g.ndim = 2;
             g.n[0] = Q.n0;
             g.n[1] = Q.n1;

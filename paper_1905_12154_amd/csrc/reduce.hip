@@ -366,14 +366,19 @@ ctrl_kernel(DevState *st, const double *__restrict__ partials, const double *__r
 // The controller of every pair of a batch: one workgroup per pair, each with
 // its pair's state, partials and counts (the deposition's partial count is
 // the number of its joint-list workgroups that visited the pair).
+// A pair that stops here also sets its bit of the table's stop mask, which
+// the other multi-pair kernels test (one load from the table head instead of
+// a load of the pair's state pointer and then of its flag).
 __global__ void __launch_bounds__(kRedBlock)
-ctrl_multi_kernel(const BatchHead *__restrict__ tab, int role, int mode)
+ctrl_multi_kernel(BatchHead *__restrict__ tab, int role, int mode)
 {
     const PairDev &P = reinterpret_cast<const PairDev *>(tab + 1)[blockIdx.x];
     CtrlParams prm = P.cp;
     const int ent = (role ? P.tiles_nu : P.tiles_mu)[0];
     prm.nsplat = ent < tab->splat_grid ? ent : tab->splat_grid;
     ctrl_body(P.st, P.part, P.gpart, mode, prm, P.trace);
+    __syncthreads();
+    if (threadIdx.x == 0 && P.st->done) atomicOr(&tab->done_mask, 1ull << blockIdx.x);
 }
 
 // One wave, lane p for pair p (np <= kBatchChunk = 64): the stop flags as a
@@ -400,7 +405,7 @@ hipError_t launch_batch_done(BatchHead *tab, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_multi(const BatchHead *tab, int np, int role, int mode, hipStream_t stream)
+hipError_t launch_ctrl_multi(BatchHead *tab, int np, int role, int mode, hipStream_t stream)
 {
     if (np < 1 || np > kBatchChunk) return hipErrorInvalidValue;
     hipLaunchKernelGGL(ctrl_multi_kernel, dim3(np), dim3(kRedBlock), 0, stream, tab, role, mode);

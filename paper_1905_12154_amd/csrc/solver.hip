@@ -1042,7 +1042,11 @@ static bfm_status batched_multi_impl(int np, const bfm_plan *P, const void *cons
         it = maxit;
     }
     // the last head (no-op for stopped pairs), then the outputs, on the full tables
-    if (compacted && (bst = upload(full)) != BFM_OK) return bst;
+    // (their stop masks gathered again from the pairs' flags)
+    if (compacted) {
+        if ((bst = upload(full)) != BFM_OK) return bst;
+        for (const MultiChunk &c : full) HIP_TRY(launch_batch_done(c.tab, s));
+    }
     for (const MultiChunk &c : full) {
         const int cnp = (int)c.pair.size();
         HIP_TRY(multi_head<T>(c, 0, s));
