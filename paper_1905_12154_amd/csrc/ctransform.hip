@@ -24,7 +24,7 @@
 //      joining edge supports both hulls) and relinks;
 //   4. every surviving vertex k, whose hull predecessor is p, is optimal for
 //      the integer slopes i >= (w_k - w_p)/(k - p); it writes k at that start
-//      index (atomic max), and a prefix maximum over i (wave shuffles) gives
+//      index (atomic max), and a prefix maximum over i (DPP inside a wave) gives
 //      the optimal vertex of every output;
 //   5. the output is re-evaluated directly as (i-k)^2 h^2/2 + u_k.
 // LDS rows are padded by one slot every 16 entries so that the lane-strided
@@ -214,7 +214,15 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
             if (p == kNone) {
                 st[c] = 0;
             } else if (p >= 0) {
-                T s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) / T(j - p);
+                // float32: the hardware reciprocal (1 ulp) instead of a
+                // correctly rounded division; s is a rounded crossing slope
+                // either way, and an output within rounding of it may take
+                // either of two candidates whose values agree to rounding
+                T s;
+                if constexpr (sizeof(T) == 4)
+                    s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) * __builtin_amdgcn_rcpf(T(j - p));
+                else
+                    s = T(0.5) * T(j + p) + n2 * (u[c] - v[padi(p)]) / T(j - p);
                 s = fmin(fmax(s, T(-1)), T(n));
                 const int si = (int)ceil(s);
                 st[c] = si < 0 ? 0 : si;
@@ -241,17 +249,31 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
         if (j0 + c < j1) m = max(m, mk[padi(j0 + c)]);
         loc[c] = m;
     }
-    // inclusive scan over the lanes of this line: shuffles inside a wave
-    // (segments of tpl lanes when tpl < 64), wave totals through LDS
+    // inclusive scan over the lanes of this line: inside a whole wave by DPP
+    // (row shifts by 1, 2, 4, 8 within rows of 16 lanes, then the broadcasts
+    // of lane 15 and lane 31 into the following rows; lanes without a source
+    // keep -1), in segments of tpl < 64 lanes by shuffles; wave totals through
+    // LDS
     const int seg = tpl < kWave ? tpl : kWave;
     int incl = m;
+    int excl;
+    if (seg == kWave) {
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x111, 0xf, 0xf, false));   // row_shr:1
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x112, 0xf, 0xf, false));   // row_shr:2
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x114, 0xf, 0xf, false));   // row_shr:4
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x118, 0xf, 0xf, false));   // row_shr:8
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x142, 0xa, 0xf, false));   // row_bcast:15
+        incl = max(incl, __builtin_amdgcn_update_dpp(-1, incl, 0x143, 0xc, 0xf, false));   // row_bcast:31
+        excl = __builtin_amdgcn_update_dpp(-1, incl, 0x138, 0xf, 0xf, false);              // wave_shr:1
+    } else {
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int o = __shfl_up(incl, off, seg);
-        if (off < seg && (t % seg) >= off) incl = max(incl, o);
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int o = __shfl_up(incl, off, seg);
+            if (off < seg && (t % seg) >= off) incl = max(incl, o);
+        }
+        excl = __shfl_up(incl, 1, seg);
+        if (t % seg == 0) excl = -1;
     }
-    int excl = __shfl_up(incl, 1, seg);
-    if (t % seg == 0) excl = -1;
     if (tpl > kWave) {
         const int tid = threadIdx.x;
         const int w = tid / kWave;
