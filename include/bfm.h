@@ -188,7 +188,7 @@ bfm_status bfm_grad_batched(int32_t npairs, const bfm_plan *plans, const void *c
                             void *const *workspaces, const size_t *ws_bytes, void *stream);
 
 /* Autotuner: times the candidate launch shapes of the c-transform line
- * kernel for every axis of the plan (points per lane 4, 8 or 16; on strided
+ * kernel for every axis of the plan (points per lane 4, 8, 12 or 16; on strided
  * axes one, two or four lines per workgroup; one line group per workgroup or
  * persistent prefetching workgroups), axis by axis in the order of a
  * transform, on `sample` (a device potential of N elements, e.g. the

@@ -83,8 +83,12 @@ template <typename V, typename T> __device__ __forceinline__ void vset(V &x, int
 }
 
 // Largest workgroup a (C, LPB) instantiation is launched with: lines of at
-// most 4096 points take tpl <= 4096 / C lanes (a power of two).
-constexpr int ct_max_threads(int C, int LPB) { return LPB * (4096 / C) < 1024 ? LPB * (4096 / C) : 1024; }
+// most 4096 points take tpl lanes, the next power of two >= 4096 / C.
+constexpr int ct_pow2_at_least(int x) { return x <= 1 ? 1 : 2 * ct_pow2_at_least((x + 1) / 2); }
+constexpr int ct_max_threads(int C, int LPB)
+{
+    return LPB * ct_pow2_at_least((4096 + C - 1) / C) < 1024 ? LPB * ct_pow2_at_least((4096 + C - 1) / C) : 1024;
+}
 
 // Wait for the lanes of one wave around LDS traffic, without a workgroup
 // barrier: a wave's LDS operations are performed in issue order, so only the
@@ -762,6 +766,8 @@ static hipError_t launch_ct_axis_blk(const T *in, T *out, int n, int inner, long
     BFM_CT_CASE(8, 8) BFM_CT_CASE(8, 16) BFM_CT_CASE(8, 32) BFM_CT_CASE(8, 64) BFM_CT_CASE(16, 2)
     BFM_CT_CASE(16, 8) BFM_CT_CASE(16, 16) BFM_CT_CASE(16, 32) BFM_CT_CASE(16, 64) BFM_CT_CASE(4, 1)
     BFM_CT_CASE(4, 2) BFM_CT_CASE(4, 4) BFM_CT_CASE(4, 8) BFM_CT_CASE(4, 16) BFM_CT_CASE(4, 32) BFM_CT_CASE(4, 64)
+    BFM_CT_CASE(12, 1) BFM_CT_CASE(12, 2) BFM_CT_CASE(12, 4) BFM_CT_CASE(12, 8) BFM_CT_CASE(12, 16)
+    BFM_CT_CASE(12, 32) BFM_CT_CASE(12, 64)
 #undef BFM_CT_CASE
     return hipErrorInvalidValue;
 }

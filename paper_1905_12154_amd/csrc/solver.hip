@@ -1214,7 +1214,7 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
             continue;
         }
         std::vector<CtCfg> cand;
-        for (int C : {4, 8, 16})
+        for (int C : {4, 8, 12, 16})
             for (int lpb : inner > 1 ? std::vector<int>{1, 2, 4} : std::vector<int>{0})
                 for (int pers : {1, 2}) {
                     if ((n + C - 1) / C > 1024) continue;
@@ -1402,9 +1402,10 @@ extern "C" bfm_status bfm_plan_set_tuning(bfm_plan plan, const int32_t *cfg9)
     CtCfg c[3];
     for (int a = 0; a < 3; ++a) {
         const int C = cfg9[3 * a], lpb = cfg9[3 * a + 1], pers = cfg9[3 * a + 2];
-        if ((C != 0 && C != 4 && C != 8 && C != 16) || (lpb != 0 && lpb != 1 && lpb != 2 && lpb != 4) || pers < 0 || pers > 2)
+        if ((C != 0 && C != 4 && C != 8 && C != 12 && C != 16) || (lpb != 0 && lpb != 1 && lpb != 2 && lpb != 4) ||
+            pers < 0 || pers > 2)
             return fail(BFM_EINVAL,
-                        "tuning of axis %d: points per lane %d (0, 4, 8, 16), lines %d (0, 1, 2, 4), mode %d (0-2)", a, C,
+                        "tuning of axis %d: points per lane %d (0, 4, 8, 12, 16), lines %d (0, 1, 2, 4), mode %d (0-2)", a, C,
                         lpb, pers);
         if (a < plan->g.ndim && C != 0 && (plan->g.n[a] + C - 1) / C > 1024)
             return fail(BFM_EINVAL, "tuning of axis %d: %d points per lane do not cover %d points", a, C, plan->g.n[a]);

@@ -78,7 +78,7 @@ def _ct_modes(shape, esz):
         return ((4 * npad * esz + 8 * npad * 2 + 3) & ~3) + 32 * tpl <= 150 * 1024
 
     out = []
-    for C in (4, 8, 16):
+    for C in (4, 8, 12, 16):
         if any(C * 1024 < n for n in shape):
             continue
         for lpb in (1, 2, 4):
@@ -125,7 +125,8 @@ def test_ctransform_every_launch_mode(shape, dtype):
 
 def test_set_tuning_rejects_bad_values():
     plan = bfm.Plan((64, 4096), torch.float32)
-    for bad in ([(12, 0, 0), (0, 0, 0)], [(8, 3, 0), (0, 0, 0)], [(8, 4, 3), (0, 0, 0)], [(0, 0, 0), (2, 0, 0)]):
+    for bad in ([(6, 0, 0), (0, 0, 0)], [(12, 0, 0), (6000, 0, 0)], [(8, 3, 0), (0, 0, 0)],
+                [(8, 4, 3), (0, 0, 0)], [(0, 0, 0), (2, 0, 0)]):
         with pytest.raises(bfm.BFMError) as e:
             plan.set_tuning(bad)
         assert e.value.status == bfm.BFM_EINVAL
