@@ -59,6 +59,31 @@ def test_solve_parity_production_shapes_f64(shape, C):
     assert np.max(np.abs(host(r.psi) - o.psi)) <= 1e-7
 
 
+
+def test_solve_parity_production_shapes_3d_f64():
+    """3D with persistent prefetching workgroups on every axis (the launch
+    shapes of the float32 384^3 path), in float64 against the oracle,
+    including the per-iteration trace of J(phi_{n+1/2}) and I(psi_{n+1})."""
+    rng = np.random.default_rng(22)
+    shape = (48, 36, 32)
+    mu = wl.random_gaussian_mixture(shape, 3, rng)
+    nu = wl.random_gaussian_mixture(shape, 4, rng)
+    plan = bfm.Plan(shape, torch.float64, max_iters=8)
+    plan.set_tuning([(4, 4, 2), (4, 4, 2), (4, 0, 2)])
+    r = plan.solve(cuda(mu), cuda(nu))
+    o = ob.solve(mu, nu, ob.Params(max_iters=8))
+    assert r.iters == o.iters == 8
+    assert abs(r.dual - o.dual) <= 1e-10
+    assert abs(r.primal - o.primal) <= 1e-10
+    assert r.sigma == pytest.approx(o.sigma, rel=1e-12)
+    for a in range(3):
+        assert np.max(np.abs(host(r.T[a]) - o.T[a])) * shape[a] <= 1e-3
+    tr = plan.trace(DEV)
+    ot = o.trace
+    for k in range(8):
+        assert tr[k]["J_half"] == pytest.approx(ot[k]["J_half"], rel=1e-10, abs=1e-12)
+        assert tr[k]["I_new"] == pytest.approx(ot[k]["I_new"], rel=1e-10, abs=1e-12)
+
 def test_interpolant_f32_elementwise():
     """float32 frames against the float64 oracle on the same float32 input
     potential, element by element.  The float32 c-transform is exact to a few
