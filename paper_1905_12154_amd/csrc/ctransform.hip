@@ -40,6 +40,14 @@ constexpr short kNone = -1;
 constexpr short kDead = -2;
 
 __device__ __forceinline__ int padi(int j) { return j + (j >> 4); }
+// padi(j0 + c) for the c-th of a lane's own C points (j0 = lane * C): with C
+// a power of two up to 16 the lane's points share one pad count, so the
+// index is padi(j0) + c and the C accesses differ only in their offsets.
+template <int C> __device__ __forceinline__ int lane_padi(int pb, int j0, int c)
+{
+    if constexpr (C <= 16 && (C & (C - 1)) == 0) return pb + c;
+    else return padi(j0 + c);
+}
 __host__ __device__ inline int padded_len(int n) { return n + (n >> 4) + 1; }
 
 // True when point k is on or above the chord from a to b (a < k < b) in the
@@ -115,6 +123,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                                              int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
 {
     const T n2 = T(n) * T(n);
+    const int pb = padi(j0);
     // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
     //    entries live in registers (u holds the lane's values), so only pops
     //    read LDS.  Each push also links the element below it forward
@@ -123,7 +132,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     if (j0 < j1) {
         int top = j0, a = -1;
         T utop = u[0], ua = T(0);
-        pv[padi(j0)] = kNone;
+        pv[pb] = kNone;
 #pragma unroll
         for (int c = 1; c < C; ++c) {
             const int j = j0 + c;
@@ -136,7 +145,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
                     a = pv[padi(top)];
                     if (a >= 0) ua = v[padi(a)];
                 }
-                pv[padi(j)] = (short)top;
+                pv[lane_padi<C>(pb, j0, c)] = (short)top;
                 nx[padi(top)] = (short)j;
                 a = top;
                 ua = utop;
@@ -214,7 +223,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
         const int j = j0 + c;
         st[c] = n;
         if (j < j1) {
-            const int p = pv[padi(j)];
+            const int p = pv[lane_padi<C>(pb, j0, c)];
             if (p == kNone) {
                 st[c] = 0;
             } else if (p >= 0) {
@@ -237,7 +246,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     int *mk = reinterpret_cast<int *>(pv);   // NP ints over this line's prev/next links
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        if (j0 + c < j1) mk[padi(j0 + c)] = -1;
+        if (j0 + c < j1) mk[lane_padi<C>(pb, j0, c)] = -1;
     line_sync(tpl);
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -250,7 +259,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     int m = -1;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        if (j0 + c < j1) m = max(m, mk[padi(j0 + c)]);
+        if (j0 + c < j1) m = max(m, mk[lane_padi<C>(pb, j0, c)]);
         loc[c] = m;
     }
     // inclusive scan over the lanes of this line: inside a whole wave by DPP
@@ -381,7 +390,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             u[c] *= sgn;
-            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
         }
     } else {
         // LPB adjacent lines are adjacent in memory along every grid row
@@ -406,7 +415,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
+        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[lane_padi<C>(padi(j0), j0, c)] : T(0);
     }
     // rows: each lane staged only its own points, which the local hull reads
     // back itself; the merge rounds synchronise before reading other lanes'
@@ -434,7 +443,7 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
         __syncthreads();
         const bool vec = LPB == 4 && (inner & 3) == 0 && (L0 % inner) + 4 <= inner && L0 + 4 <= nlines && out_al;
         const long long base0 = line_base(L0, n, inner);
@@ -544,7 +553,7 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
             }
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+                if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
             // no barrier: the local hull reads only the lane's own points and
             // the merge rounds synchronise before reading other lanes'
         } else {
@@ -559,7 +568,7 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
             }
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
+            for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[lane_padi<C>(padi(j0), j0, c)] : T(0);
         }
         if (G0 + step < nlines) fetch(G0 + step);   // in flight during the transform
 
@@ -586,7 +595,7 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
             line_sync(tpl);
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+                if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
             __syncthreads();
             // plain: row j of the group at line_base + j * inner; blocked: the
             // group's run starts at G0 * n (G0 = 4 x group index), 4 per row
@@ -933,7 +942,7 @@ __device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             u[c] *= sgn;
-            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
         }
     } else {
         // lines L0 .. L0 + lpb - 1 are adjacent columns: four per 16-byte
@@ -961,7 +970,7 @@ __device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[padi(j0 + c)] : T(0);
+        for (int c = 0; c < C; ++c) u[c] = j0 + c < j1 ? v[lane_padi<C>(padi(j0), j0, c)] : T(0);
     }
 
     if (n <= kMultiCtDirect) {   // uniform: one pair per workgroup
@@ -988,7 +997,7 @@ __device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (j0 + c < j1) v[padi(j0 + c)] = u[c];
+            if (j0 + c < j1) v[lane_padi<C>(padi(j0), j0, c)] = u[c];
         __syncthreads();
         if (lpb >= 4) {
             const int nv = lpb / 4;

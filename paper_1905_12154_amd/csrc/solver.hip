@@ -1255,29 +1255,34 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
         }
         std::swap(f, nxt);
     }
-    // 2D: the per-axis choice against both axes on the persistent kernel,
-    // which lets the transform pass the column-blocked intermediate; timed
-    // as whole transforms
-    if (out == BFM_OK && g.ndim == 2 && (P->ct_cfg[0].pers != 2 || P->ct_cfg[1].pers != 2)) {
+    // 2D: the per-axis choice against the column-blocked form (both axes on
+    // the persistent kernel, four-column groups, which lets the transform
+    // pass the column-blocked intermediate); timed as whole transforms
+    if (out == BFM_OK && g.ndim == 2) {
         const T *src = sample;
         if (src == nullptr) {
             hipLaunchKernelGGL((tune_field_kernel<T>), dim3(1024), dim3(256), 0, s, (T *)w.f, g);
             HIP_TRY(hipGetLastError());
             src = (const T *)w.f;
         }
-        // candidates: the per-axis choice, then both axes persistent with the
-        // tuned column shape and each row width
-        CtCfg cand[4][3];
+        // candidates: the per-axis choice, then the blocked form with the
+        // tuned column width (and 16) and each row width
+        CtCfg cand[8][3];
         int ncand = 0;
         for (int a = 0; a < 3; ++a) cand[0][a] = P->ct_cfg[a];
         ncand = 1;
-        for (int C : {8, 16}) {
-            if ((g.n[1] + C - 1) / C > 1024) continue;
-            for (int a = 0; a < 3; ++a) cand[ncand][a] = P->ct_cfg[a];
-            cand[ncand][0].pers = 2;
-            cand[ncand][1].pers = 2;
-            cand[ncand][1].C = C;
-            ++ncand;
+        for (int C0 : {P->ct_cfg[0].C, 16}) {
+            if (C0 == 0 || (C0 == 16 && P->ct_cfg[0].C == 16 && ncand > 1)) continue;
+            for (int C : {8, 16}) {
+                if ((g.n[1] + C - 1) / C > 1024 || (g.n[0] + C0 - 1) / C0 > 1024) continue;
+                for (int a = 0; a < 3; ++a) cand[ncand][a] = P->ct_cfg[a];
+                cand[ncand][0].C = C0;
+                cand[ncand][0].lpb = 4;
+                cand[ncand][0].pers = 2;
+                cand[ncand][1].C = C;
+                cand[ncand][1].pers = 2;
+                ++ncand;
+            }
         }
         T *scratch = src == (const T *)w.f ? (T *)w.rho : (T *)w.f;
         float best = 1e30f;
@@ -1292,6 +1297,9 @@ static bfm_status autotune_impl(bfm_plan P, const T *sample, const Ws &w, hipStr
             if (hipEventSynchronize(b) != hipSuccess || e != hipSuccess) continue;
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, a, b);
+            // candidates in the blocked form are credited 5%: in a solve they
+            // also fuse <q, src> into the row pass, which this timing does not see
+            if (ct_blocked_applies<T>(g, src, scratch, o, cf)) ms *= 0.95f;
             if (ms < best) {
                 best = ms;
                 pick = c;
