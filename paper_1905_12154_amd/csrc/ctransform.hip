@@ -118,25 +118,29 @@ __device__ __forceinline__ void line_sync(int tpl) {
 // and, for the lane's points [j0, j1), in u; on return u holds the output.
 // Touches only this line's LDS (v, pv/nx, GH/GT) and wave_tot; all lanes of
 // the workgroup call it (its block barriers are uniform).
-template <typename T, int C>
+//
+// FULL: every lane of the line holds all C of its points (n = tpl C), so the
+// per-point range tests drop out.
+template <typename T, int C, bool FULL = false>
 __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, short *nx, int *GH, int *GT,
                                              int *wave_tot, int j0, int j1, int t, int tpl, int l, int n, T h)
 {
     const T n2 = T(n) * T(n);
     const int pb = padi(j0);
+    auto has = [&](int c) { return FULL || j0 + c < j1; };
     // 2. lane-local lower hull of points [j0, j1): a stack scan whose top two
     //    entries live in registers (u holds the lane's values), so only pops
     //    read LDS.  Each push also links the element below it forward
     //    (a later push over the same element overwrites a popped successor),
     //    so the forward links of the final stack need no second walk.
-    if (j0 < j1) {
+    if (FULL || j0 < j1) {
         int top = j0, a = -1;
         T utop = u[0], ua = T(0);
         pv[pb] = kNone;
 #pragma unroll
         for (int c = 1; c < C; ++c) {
             const int j = j0 + c;
-            if (j < j1) {
+            if (has(c)) {
                 const T uj = u[c];
                 while (a >= 0 && above_chord(a, top, j, ua, utop, uj, n2)) {
                     pv[padi(top)] = kDead;
@@ -222,7 +226,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     for (int c = 0; c < C; ++c) {
         const int j = j0 + c;
         st[c] = n;
-        if (j < j1) {
+        if (has(c)) {
             const int p = pv[lane_padi<C>(pb, j0, c)];
             if (p == kNone) {
                 st[c] = 0;
@@ -246,7 +250,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     int *mk = reinterpret_cast<int *>(pv);   // NP ints over this line's prev/next links
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        if (j0 + c < j1) mk[lane_padi<C>(pb, j0, c)] = -1;
+        if (has(c)) mk[lane_padi<C>(pb, j0, c)] = -1;
     line_sync(tpl);
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -259,7 +263,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
     int m = -1;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        if (j0 + c < j1) m = max(m, mk[lane_padi<C>(pb, j0, c)]);
+        if (has(c)) m = max(m, mk[lane_padi<C>(pb, j0, c)]);
         loc[c] = m;
     }
     // inclusive scan over the lanes of this line: inside a whole wave by DPP
@@ -300,7 +304,7 @@ __device__ __forceinline__ void ct_line_core(T (&u)[C], const T *v, short *pv, s
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int j = j0 + c;
-        if (j < j1) {
+        if (has(c)) {
             const int k = max(excl, loc[c]);
             const T d = T(j - k) * h;
             u[c] = T(0.5) * d * d + v[padi(k)];
@@ -420,7 +424,10 @@ ct_lines_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inner,
     // rows: each lane staged only its own points, which the local hull reads
     // back itself; the merge rounds synchronise before reading other lanes'
 
-    ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
+    if (n == tpl * C)   // uniform
+        ct_line_core<T, C, true>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
+    else
+        ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
 
     if (inner == 1) {
         const bool vec = (n & 3) == 0 && (C & 3) == 0 && out_al;
@@ -572,7 +579,10 @@ ct_lines_pf_kernel(const T *__restrict__ in, T *__restrict__ out, int n, int inn
         }
         if (G0 + step < nlines) fetch(G0 + step);   // in flight during the transform
 
-        ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
+        if (n == tpl * C)   // uniform
+            ct_line_core<T, C, true>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
+        else
+            ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, h);
 
         if constexpr (!STRIDED) {
             if (L < nlines && j0 < j1) {
@@ -977,7 +987,11 @@ __device__ __forceinline__ void ct_multi_body(const PairDev &P, const BatchIdx &
         if (!STRIDED) line_sync(tpl);   // the line's values, staged by its other lanes
         ct_line_direct<T, C>(u, v, j0, j1, n, T(1.0) / T(n));
     } else {
-        ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, T(1.0) / T(n));
+        const T hn = T(1.0) / T(n);
+        if (n == tpl * C)   // uniform: one pair per workgroup
+            ct_line_core<T, C, true>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, hn);
+        else
+            ct_line_core<T, C>(u, v, pv, pv + NP, GH, GH + tpl, wave_tot, j0, j1, t, tpl, l, n, hn);
     }
 
     double dacc = 0.0;
