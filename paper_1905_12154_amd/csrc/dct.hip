@@ -153,6 +153,17 @@ __device__ __forceinline__ cpx<T> global_cpx(const cpx<T> *tab, int i) {
 // write (barrier); lines of one workgroup advance together.  tstep = n / (p R)
 // comes from the caller; the radix-3 stages run last, so p is a power of two
 // in every other stage and k = i mod p is a mask there.
+// Division of a coefficient by the Laplacian's eigenvalue: float32 takes the
+// hardware reciprocal (1 ulp), which is within the rounding the float32
+// coefficients already carry; float64 divides.
+template <typename T> __device__ __forceinline__ T lap_div(T x, T l)
+{
+    if constexpr (sizeof(T) == 4)
+        return x * __builtin_amdgcn_rcpf(l);
+    else
+        return x / l;
+}
+
 template <typename T, int VMAX, int R>
 __device__ __attribute__((noinline)) void fft_stage(int off, int n, int p, int tstep, int lt, int bd,
                                                     const cpx<T> *__restrict__ tw) {
@@ -590,8 +601,8 @@ dct_lines_body(const T *a, T *b, T *out, const T *base, const double *scale, con
                 dct2_post_v(z2, z1, wq2[q], Xa2, Xb2);
                 const T la1 = l01[q] + lra, lb1 = l01[q] + lrb;
                 const T la2 = l02[q] + lra, lb2 = l02[q] + lrb;
-                const T ya1 = la1 > T(0) ? Xa1 / la1 : T(0), yb1 = lb1 > T(0) ? Xb1 / lb1 : T(0);
-                const T ya2 = la2 > T(0) ? Xa2 / la2 : T(0), yb2 = lb2 > T(0) ? Xb2 / lb2 : T(0);
+                const T ya1 = la1 > T(0) ? lap_div(Xa1, la1) : T(0), yb1 = lb1 > T(0) ? lap_div(Xb1, lb1) : T(0);
+                const T ya2 = la2 > T(0) ? lap_div(Xa2, la2) : T(0), yb2 = lb2 > T(0) ? lap_div(Xb2, lb2) : T(0);
                 const double wk1 = (u == 0 ? 1.0 : 2.0) * inv_n, wk2 = 2.0 * inv_n;
                 if (hasa) gacc += wk1 * wra * (double)Xa1 * (double)ya1;
                 if (hasb) gacc += wk1 * wrb * (double)Xb1 * (double)yb1;
